@@ -1,0 +1,601 @@
+// nfq_api.hip -- C ABI of the near-field correction generator (include/nfq.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nfq.h"
+#include "kernels.hpp"
+#include "tables.hpp"
+
+using namespace nfq;
+
+struct nfq_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    RefData ref[9];
+    double *dV[9] = {}, *duv[9] = {}, *dw[9] = {};
+    double *drule = nullptr;         // [64][3]
+    double *dglr = nullptr, *dgla = nullptr;
+    int nr = 0, na = 0;
+    std::string err;
+};
+
+struct nfq_plan {
+    nfq_ctx *ctx = nullptr;
+    Problem pb{};
+    int64_t nnz = 0, npairs = 0;
+    int64_t *row_ptr = nullptr;      // caller's
+    // scratch
+    int64_t *rowlen = nullptr, *npair = nullptr, *pair_ptr = nullptr;
+    std::vector<int64_t *> scan_tmp; // per level: a_tot, b_tot, a_off, b_off
+    std::vector<int64_t> scan_n;
+    int32_t *pair_tgt = nullptr, *pair_patch = nullptr;
+    int8_t *pair_self = nullptr;
+    int64_t *pair_off = nullptr;
+    int32_t *grp = nullptr;
+    int64_t grp_len = 0;
+    int64_t seg_start_h[18] = {}, seg_len_h[18] = {}, count_h[18] = {};
+    int64_t *seg_start = nullptr;
+    unsigned long long *cursor = nullptr;
+    double *coef = nullptr, *tau = nullptr;
+    double *stack = nullptr;
+    int64_t stack_waves = 0;
+    int *flags = nullptr;
+    unsigned long long *stats = nullptr;
+    unsigned long long *counts = nullptr;
+    int present_mask = 0;
+    int max_degree = 0;
+    int value_kind = -1;  // value type of the last generate: 0 double, 1 complex128
+    hipEvent_t ev[2 * 5 * 9] = {};  // phase timing events (begin, end) x phase x degree
+    bool ev_ok = false;
+};
+
+enum Phase { kPhBuilder = 0, kPhPrep, kPhSelf, kPhNear, kPhWeights, kNumPhases };
+
+struct Timer {
+    nfq_plan *pl;
+    bool on;
+    int used[kNumPhases * 9] = {};
+    void begin(int ph, int slot, hipStream_t st)
+    {
+        if (on) { (void)hipEventRecord(pl->ev[2 * (ph * 9 + slot)], st); used[ph * 9 + slot] = 1; }
+    }
+    void end(int ph, int slot, hipStream_t st)
+    {
+        if (on) (void)hipEventRecord(pl->ev[2 * (ph * 9 + slot) + 1], st);
+    }
+    double total(int ph)
+    {
+        double t = 0.0;
+        for (int s = 0; s < 9; ++s)
+            if (used[ph * 9 + s]) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, pl->ev[2 * (ph * 9 + s)], pl->ev[2 * (ph * 9 + s) + 1]) == hipSuccess)
+                    t += ms;
+            }
+        return t;
+    }
+};
+
+namespace {
+
+nfq_status fail(nfq_ctx *ctx, nfq_status s, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), NFQ_ERR_HIP, std::string(#expr " -> ") + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, size_t n)
+{
+    return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
+
+int64_t pad16(int64_t n) { return (n + 15) / 16 * 16; }
+
+// Exclusive scan of a_in, b_in (length n) into a_out, b_out (length n + 1).
+nfq_status run_scan(nfq_plan *pl, int64_t n, const int64_t *a_in, const int64_t *b_in,
+                    int64_t *a_out, int64_t *b_out)
+{
+    hipStream_t st = pl->ctx->stream;
+    // level sizes
+    std::vector<int64_t> sizes;
+    int64_t m = n;
+    while (true) {
+        sizes.push_back(m);
+        if (m <= kScanTile) break;
+        m = (m + kScanTile - 1) / kScanTile;
+    }
+    // level 0 scans the input; level k scans the tile totals of level k-1
+    const int64_t *ia = a_in, *ib = b_in;
+    int64_t *oa = a_out, *ob = b_out;
+    std::vector<int64_t *> outs_a, outs_b;
+    for (size_t lv = 0; lv < sizes.size(); ++lv) {
+        const int64_t len = sizes[lv];
+        const int64_t tiles = (len + kScanTile - 1) / kScanTile;
+        int64_t *ta = pl->scan_tmp[4 * lv + 0], *tb = pl->scan_tmp[4 * lv + 1];
+        int64_t *na = pl->scan_tmp[4 * lv + 2], *nb2 = pl->scan_tmp[4 * lv + 3];
+        if (len > 0)
+            hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, len, ia,
+                               ib, oa, ob, ta, tb);
+        outs_a.push_back(oa);
+        outs_b.push_back(ob);
+        ia = ta;
+        ib = tb;
+        oa = na;
+        ob = nb2;
+    }
+    // propagate tile offsets downwards
+    for (int lv = (int)sizes.size() - 2; lv >= 0; --lv) {
+        const int64_t len = sizes[lv];
+        hipLaunchKernelGGL(k_scan_add, dim3(nblk(len, 256)), dim3(256), 0, st, len, outs_a[lv],
+                           outs_b[lv], outs_a[lv + 1], outs_b[lv + 1]);
+    }
+    hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(64), 0, st, n, a_in, b_in, a_out, b_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(pl->ctx, NFQ_ERR_HIP, hipGetErrorString(e));
+    return NFQ_OK;
+}
+
+DegTab make_tab(const nfq_ctx *ctx)
+{
+    DegTab t{};
+    for (int d = 0; d < 9; ++d) {
+        t.V[d] = ctx->dV[d];
+        t.uv[d] = ctx->duv[d];
+        t.w[d] = ctx->dw[d];
+        t.normV[d] = ctx->ref[d].normV;
+        t.present[d] = ctx->dV[d] != nullptr;
+    }
+    return t;
+}
+
+nfq_status check_flags(nfq_ctx *ctx, const int *hflags)
+{
+    if (hflags[kFlagInvalid]) return fail(ctx, NFQ_ERR_INVALID_ARG, "invalid near list or node id");
+    if (hflags[kFlagNotRegistered])
+        return fail(ctx, NFQ_ERR_NOT_REGISTERED, "a patch uses an unregistered degree");
+    if (hflags[kFlagDegenerate]) return fail(ctx, NFQ_ERR_DEGENERATE_PATCH, "degenerate patch (J <= 0)");
+    if (hflags[kFlagSingular])
+        return fail(ctx, NFQ_ERR_SINGULAR_PAIR, "a near target coincides with a patch point");
+    return NFQ_OK;
+}
+
+template <int D, bool CPLX>
+void launch_quad(const nfq_plan *pl, QuadArgs qa, int64_t near_seg, int64_t near_cnt,
+                 int64_t self_seg, int64_t self_cnt, hipStream_t st, Timer &tm)
+{
+    using S = QuadShape<D, CPLX>;
+    if (self_cnt > 0) {
+        qa.seg = self_seg;
+        qa.count = self_cnt;
+        const unsigned blocks = nblk(self_cnt, S::WPB);
+        tm.begin(kPhSelf, D, st);
+        hipLaunchKernelGGL((k_self<D, CPLX>), dim3(blocks), dim3(64 * S::WPB), 0, st, qa);
+        tm.end(kPhSelf, D, st);
+    }
+    if (near_cnt > 0) {
+        qa.seg = near_seg;
+        qa.count = near_cnt;
+        const int64_t max_blocks = pl->stack_waves / S::WPB;
+        const unsigned blocks = (unsigned)std::min<int64_t>(nblk(near_cnt, S::WPB), max_blocks);
+        tm.begin(kPhNear, D, st);
+        hipLaunchKernelGGL((k_near<D, CPLX>), dim3(blocks), dim3(64 * S::WPB), 0, st, qa);
+        tm.end(kPhNear, D, st);
+    }
+    const int64_t tot = near_cnt + self_cnt;  // both padded to 16, contiguous
+    if (tot > 0) {
+        tm.begin(kPhWeights, D, st);
+        hipLaunchKernelGGL((k_weights<D, CPLX>), dim3(nblk(tot, 16)), dim3(256), 0, st, qa.grp,
+                           near_seg, tot, qa.pair_off, pl->ctx->dV[D], qa.val);
+        tm.end(kPhWeights, D, st);
+    }
+}
+
+template <bool CPLX>
+void launch_degree(int d, const nfq_plan *pl, const QuadArgs &qa, int64_t ns, int64_t nc,
+                   int64_t ss, int64_t sc, hipStream_t st, Timer &tm)
+{
+    switch (d) {
+    case 1: launch_quad<1, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
+    case 2: launch_quad<2, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
+    case 3: launch_quad<3, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
+    case 4: launch_quad<4, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
+    case 5: launch_quad<5, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
+    case 6: launch_quad<6, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
+    case 7: launch_quad<7, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
+    case 8: launch_quad<8, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
+    default: break;
+    }
+}
+
+nfq_status ensure_self_rule(nfq_ctx *ctx, int nr, int na)
+{
+    if (ctx->nr == nr && ctx->na == na && ctx->dglr) return NFQ_OK;
+    std::vector<double> x, w;
+    std::vector<double> buf;
+    if (ctx->dglr) (void)hipFree(ctx->dglr);
+    if (ctx->dgla) (void)hipFree(ctx->dgla);
+    ctx->dglr = ctx->dgla = nullptr;
+    gauss_rule(nr, 0, 0, x, w);
+    buf.resize(2 * nr);
+    for (int i = 0; i < nr; ++i) { buf[2 * i] = x[i]; buf[2 * i + 1] = w[i]; }
+    HIP_TRY(ctx, dalloc(&ctx->dglr, buf.size()));
+    HIP_TRY(ctx, hipMemcpy(ctx->dglr, buf.data(), buf.size() * 8, hipMemcpyHostToDevice));
+    gauss_rule(na, 0, 0, x, w);
+    buf.resize(2 * na);
+    for (int i = 0; i < na; ++i) { buf[2 * i] = x[i]; buf[2 * i + 1] = w[i]; }
+    HIP_TRY(ctx, dalloc(&ctx->dgla, buf.size()));
+    HIP_TRY(ctx, hipMemcpy(ctx->dgla, buf.data(), buf.size() * 8, hipMemcpyHostToDevice));
+    ctx->nr = nr;
+    ctx->na = na;
+    return NFQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nfq_status_str(nfq_status s)
+{
+    switch (s) {
+    case NFQ_OK: return "NFQ_OK";
+    case NFQ_WARN_NONCONVERGED: return "NFQ_WARN_NONCONVERGED";
+    case NFQ_ERR_INVALID_ARG: return "NFQ_ERR_INVALID_ARG";
+    case NFQ_ERR_NOT_REGISTERED: return "NFQ_ERR_NOT_REGISTERED";
+    case NFQ_ERR_DEGENERATE_PATCH: return "NFQ_ERR_DEGENERATE_PATCH";
+    case NFQ_ERR_SINGULAR_PAIR: return "NFQ_ERR_SINGULAR_PAIR";
+    case NFQ_ERR_OUT_OF_MEMORY: return "NFQ_ERR_OUT_OF_MEMORY";
+    case NFQ_ERR_HIP: return "NFQ_ERR_HIP";
+    case NFQ_ERR_UNSUPPORTED: return "NFQ_ERR_UNSUPPORTED";
+    default: return "NFQ_UNKNOWN";
+    }
+}
+
+const char *nfq_last_error(nfq_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+nfq_status nfq_create(int device, void *hip_stream, nfq_ctx **out)
+{
+    if (!out) return NFQ_ERR_INVALID_ARG;
+    *out = nullptr;
+    nfq_ctx *ctx = new (std::nothrow) nfq_ctx;
+    if (!ctx) return NFQ_ERR_OUT_OF_MEMORY;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return NFQ_ERR_HIP;
+    }
+    std::vector<double> rule;
+    conical_rule(kNG, rule);
+    if (dalloc(&ctx->drule, rule.size()) != hipSuccess ||
+        hipMemcpy(ctx->drule, rule.data(), rule.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+        delete ctx;
+        return NFQ_ERR_HIP;
+    }
+    if (ensure_self_rule(ctx, 10, 16) != NFQ_OK) {
+        delete ctx;
+        return NFQ_ERR_HIP;
+    }
+    *out = ctx;
+    return NFQ_OK;
+}
+
+void nfq_destroy(nfq_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    for (int d = 0; d < 9; ++d) {
+        if (ctx->dV[d]) (void)hipFree(ctx->dV[d]);
+        if (ctx->duv[d]) (void)hipFree(ctx->duv[d]);
+        if (ctx->dw[d]) (void)hipFree(ctx->dw[d]);
+    }
+    if (ctx->drule) (void)hipFree(ctx->drule);
+    if (ctx->dglr) (void)hipFree(ctx->dglr);
+    if (ctx->dgla) (void)hipFree(ctx->dgla);
+    delete ctx;
+}
+
+nfq_status nfq_register_degree(nfq_ctx *ctx, int d, const double *ref_uv, const double *ref_w)
+{
+    if (!ctx || !ref_uv) return fail(ctx, NFQ_ERR_INVALID_ARG, "null argument");
+    if (d < 1 || d > 8) return fail(ctx, NFQ_ERR_UNSUPPORTED, "degree outside 1..8");
+    RefData r;
+    std::string msg = build_reference(d, ref_uv, ref_w, r);
+    if (!msg.empty()) return fail(ctx, NFQ_ERR_INVALID_ARG, msg);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (ctx->dV[d]) { (void)hipFree(ctx->dV[d]); (void)hipFree(ctx->duv[d]); (void)hipFree(ctx->dw[d]); }
+    ctx->dV[d] = ctx->duv[d] = ctx->dw[d] = nullptr;
+    HIP_TRY(ctx, dalloc(&ctx->dV[d], r.V.size()));
+    HIP_TRY(ctx, dalloc(&ctx->duv[d], r.uv.size()));
+    HIP_TRY(ctx, dalloc(&ctx->dw[d], r.w.size()));
+    HIP_TRY(ctx, hipMemcpy(ctx->dV[d], r.V.data(), r.V.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(ctx->duv[d], r.uv.data(), r.uv.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(ctx->dw[d], r.w.data(), r.w.size() * 8, hipMemcpyHostToDevice));
+    ctx->ref[d] = r;
+    return NFQ_OK;
+}
+
+void nfq_plan_destroy(nfq_plan *pl)
+{
+    if (!pl) return;
+    (void)hipSetDevice(pl->ctx->device);
+    void *ptrs[] = {pl->rowlen, pl->npair, pl->pair_ptr, pl->pair_tgt, pl->pair_patch, pl->pair_self,
+                    pl->pair_off, pl->grp, pl->seg_start, pl->cursor, pl->coef, pl->tau, pl->stack,
+                    pl->flags, pl->stats, pl->counts};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (int64_t *p : pl->scan_tmp)
+        if (p) (void)hipFree(p);
+    if (pl->ev_ok)
+        for (auto &e : pl->ev) (void)hipEventDestroy(e);
+    delete pl;
+}
+
+nfq_status nfq_plan_create(nfq_ctx *ctx, const nfq_surface *surf, const nfq_targets *tg,
+                           const nfq_nearlist *near, nfq_plan **out, int64_t *nnz_out,
+                           int64_t *row_ptr)
+{
+    if (!ctx || !surf || !tg || !near || !out || !nnz_out || !row_ptr)
+        return fail(ctx, NFQ_ERR_INVALID_ARG, "null argument");
+    if (surf->P <= 0 || tg->NT < 0 || !surf->degree || !surf->node_ptr || !surf->xyz ||
+        (tg->NT > 0 && (!tg->xyz || !tg->node_of_target || !near->row_ptr)))
+        return fail(ctx, NFQ_ERR_INVALID_ARG, "bad sizes or null arrays");
+    if (tg->NT >= (int64_t)INT32_MAX || surf->P >= (int64_t)INT32_MAX)
+        return fail(ctx, NFQ_ERR_UNSUPPORTED, "more than 2^31 targets or patches");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    *out = nullptr;
+    nfq_plan *pl = new (std::nothrow) nfq_plan;
+    if (!pl) return fail(ctx, NFQ_ERR_OUT_OF_MEMORY, "plan");
+    pl->ctx = ctx;
+    hipStream_t st = ctx->stream;
+    Problem &pb = pl->pb;
+    pb.P = surf->P;
+    pb.NT = tg->NT;
+    pb.degree = surf->degree;
+    pb.node_ptr = surf->node_ptr;
+    pb.xyz = surf->xyz;
+    pb.txyz = tg->xyz;
+    pb.node_of_target = tg->node_of_target;
+    pb.near_rp = near->row_ptr;
+    pb.near_patch = near->patch;
+    pl->row_ptr = row_ptr;
+    for (int d = 1; d <= 8; ++d)
+        if (ctx->dV[d]) pl->present_mask |= 1 << d;
+    auto cleanup = [&](nfq_status s) {
+        nfq_plan_destroy(pl);
+        return s;
+    };
+#define PL_TRY(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            ctx->err = std::string(#expr " -> ") + hipGetErrorString(e_);                     \
+            return cleanup(e_ == hipErrorOutOfMemory ? NFQ_ERR_OUT_OF_MEMORY : NFQ_ERR_HIP);  \
+        }                                                                                     \
+    } while (0)
+    PL_TRY(hipMemcpyAsync(&pb.N, surf->node_ptr + pb.P, 8, hipMemcpyDeviceToHost, st));
+    PL_TRY(hipStreamSynchronize(st));
+    if (pb.N <= 0 || pb.N >= (int64_t)INT32_MAX) return cleanup(fail(ctx, NFQ_ERR_INVALID_ARG, "bad node count"));
+    const int64_t NT = pb.NT;
+    PL_TRY(dalloc(&pl->rowlen, NT));
+    PL_TRY(dalloc(&pl->npair, NT));
+    PL_TRY(dalloc(&pl->pair_ptr, NT + 1));
+    PL_TRY(dalloc(&pl->flags, kNumFlags));
+    PL_TRY(dalloc(&pl->stats, kNumStats));
+    PL_TRY(dalloc(&pl->counts, 18));
+    PL_TRY(dalloc(&pl->cursor, 18));
+    PL_TRY(dalloc(&pl->seg_start, 18));
+    // scan temporaries
+    {
+        int64_t m = NT;
+        while (true) {
+            const int64_t tiles = (m + kScanTile - 1) / kScanTile;
+            for (int k = 0; k < 4; ++k) {
+                int64_t *p = nullptr;
+                PL_TRY(dalloc(&p, tiles + 1));
+                pl->scan_tmp.push_back(p);
+            }
+            if (m <= kScanTile) break;
+            m = tiles;
+        }
+    }
+    PL_TRY(hipMemsetAsync(pl->flags, 0, kNumFlags * sizeof(int), st));
+    PL_TRY(hipMemsetAsync(pl->counts, 0, 18 * 8, st));
+    if (NT > 0)
+        hipLaunchKernelGGL(k_rowlen, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, pl->present_mask,
+                           pl->rowlen, pl->npair, pl->counts, pl->flags);
+    nfq_status s = run_scan(pl, NT, pl->rowlen, pl->npair, row_ptr, pl->pair_ptr);
+    if (s != NFQ_OK) return cleanup(s);
+    int hflags[kNumFlags];
+    PL_TRY(hipMemcpyAsync(hflags, pl->flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
+    PL_TRY(hipMemcpyAsync(&pl->nnz, row_ptr + NT, 8, hipMemcpyDeviceToHost, st));
+    PL_TRY(hipMemcpyAsync(&pl->npairs, pl->pair_ptr + NT, 8, hipMemcpyDeviceToHost, st));
+    unsigned long long hc[18];
+    PL_TRY(hipMemcpyAsync(hc, pl->counts, sizeof(hc), hipMemcpyDeviceToHost, st));
+    PL_TRY(hipStreamSynchronize(st));
+    s = check_flags(ctx, hflags);
+    if (s != NFQ_OK) return cleanup(s);
+    // segments: for d = 1..8: near_d (padded to 16) then self_d (padded)
+    int64_t pos = 0;
+    for (int d = 1; d <= 8; ++d) {
+        for (int kind = 0; kind < 2; ++kind) {
+            const int key = kind * 9 + d;
+            pl->count_h[key] = (int64_t)hc[key];
+            pl->seg_start_h[key] = pos;
+            pl->seg_len_h[key] = pad16((int64_t)hc[key]);
+            pos += pl->seg_len_h[key];
+            if (hc[key] > 0) pl->max_degree = std::max(pl->max_degree, d);
+        }
+    }
+    pl->grp_len = pos;
+    const int64_t np = pl->npairs;
+    PL_TRY(dalloc(&pl->pair_tgt, np));
+    PL_TRY(dalloc(&pl->pair_patch, np));
+    PL_TRY(dalloc(&pl->pair_self, np));
+    PL_TRY(dalloc(&pl->pair_off, np));
+    PL_TRY(dalloc(&pl->grp, pl->grp_len));
+    PL_TRY(hipMemcpy(pl->seg_start, pl->seg_start_h, sizeof(pl->seg_start_h), hipMemcpyHostToDevice));
+    PL_TRY(dalloc(&pl->coef, 3 * pb.N));
+    PL_TRY(dalloc(&pl->tau, pb.P));
+    // DFS stacks for the persistent near kernel: enough wavefronts to fill the chip
+    {
+        int ncu = 0;
+        PL_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        pl->stack_waves = (int64_t)std::max(ncu, 1) * 16;
+        const int64_t esz = 8 + 2 * kNDMax;
+        PL_TRY(dalloc(&pl->stack, pl->stack_waves * kStack * esz));
+    }
+    *nnz_out = pl->nnz;
+    *out = pl;
+#undef PL_TRY
+    return NFQ_OK;
+}
+
+nfq_status nfq_generate(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *prm, int32_t *col,
+                        void *val, nfq_stats *stats)
+{
+    if (!pl || !kern || !prm || !col || !val) return fail(pl ? pl->ctx : nullptr, NFQ_ERR_INVALID_ARG, "null argument");
+    nfq_ctx *ctx = pl->ctx;
+    if (!(prm->tol > 0.0) || !(prm->loosen > 0.0) || prm->max_depth < 1 || prm->max_depth > kMaxDepth)
+        return fail(ctx, NFQ_ERR_INVALID_ARG, "tol, loosen must be > 0; max_depth in 1..32");
+    if (prm->ng != 0 && prm->ng != kNG) return fail(ctx, NFQ_ERR_UNSUPPORTED, "only ng = 8 is supported");
+    const int nr = prm->self_nr > 0 ? prm->self_nr : 10;
+    const int na = prm->self_na > 0 ? prm->self_na : 16;
+    if (nr > 64 || na > 64) return fail(ctx, NFQ_ERR_INVALID_ARG, "self rule sizes must be <= 64");
+    if (kern->k_im < 0.0) return fail(ctx, NFQ_ERR_INVALID_ARG, "Im k must be >= 0");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    nfq_status s0 = ensure_self_rule(ctx, nr, na);
+    if (s0 != NFQ_OK) return s0;
+    hipStream_t st = ctx->stream;
+    const Problem &pb = pl->pb;
+    const int64_t NT = pb.NT;
+    const bool cplx = !(kern->k_re == 0.0 && kern->k_im == 0.0 && kern->alpha_im == 0.0 &&
+                        kern->beta_im == 0.0);
+    pl->value_kind = cplx ? 1 : 0;
+    Timer tm{pl, (prm->flags & NFQ_FLAG_TIMING) != 0 && stats != nullptr};
+    if (tm.on && !pl->ev_ok) {
+        for (auto &e : pl->ev) HIP_TRY(ctx, hipEventCreate(&e));
+        pl->ev_ok = true;
+    }
+    HIP_TRY(ctx, hipMemsetAsync(pl->flags, 0, kNumFlags * sizeof(int), st));
+    HIP_TRY(ctx, hipMemsetAsync(pl->stats, 0, kNumStats * 8, st));
+    HIP_TRY(ctx, hipMemsetAsync(pl->cursor, 0, 18 * 8, st));
+    HIP_TRY(ctx, hipMemsetAsync(pl->grp, 0xff, pl->grp_len * sizeof(int32_t), st));
+    // pair / work-queue builder
+    tm.begin(kPhBuilder, 0, st);
+    if (NT > 0)
+        hipLaunchKernelGGL(k_rowlen, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, pl->present_mask,
+                           pl->rowlen, pl->npair, (unsigned long long *)nullptr, pl->flags);
+    nfq_status s = run_scan(pl, NT, pl->rowlen, pl->npair, pl->row_ptr, pl->pair_ptr);
+    if (s != NFQ_OK) return s;
+    if (NT > 0)
+        hipLaunchKernelGGL(k_pairs, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, pl->row_ptr,
+                           pl->pair_ptr, pl->pair_tgt, pl->pair_patch, pl->pair_self, pl->pair_off,
+                           col);
+    if (pl->npairs > 0)
+        hipLaunchKernelGGL(k_group, dim3(nblk(pl->npairs, 256)), dim3(256), 0, st, pl->npairs,
+                           pl->pair_patch, pl->pair_self, pb.degree, pl->seg_start, pl->cursor,
+                           pl->grp);
+    tm.end(kPhBuilder, 0, st);
+    // patch preparation
+    DegTab tab = make_tab(ctx);
+    tm.begin(kPhPrep, 0, st);
+    hipLaunchKernelGGL(k_prep, dim3(nblk(pb.P, 64)), dim3(64), 0, st, pb, tab,
+                       prm->loosen * prm->tol, pl->coef, pl->tau, pl->flags);
+    tm.end(kPhPrep, 0, st);
+    // quadratures and weights, per degree
+    QuadArgs qa{};
+    qa.pb = pb;
+    qa.tab = tab;
+    qa.kern = Kern{kern->alpha_re, kern->alpha_im, kern->beta_re, kern->beta_im, kern->k_re, kern->k_im};
+    qa.helm = (kern->k_re != 0.0 || kern->k_im != 0.0) ? 1 : 0;
+    qa.max_depth = prm->max_depth;
+    qa.rule = ctx->drule;
+    qa.glr = ctx->dglr;
+    qa.gla = ctx->dgla;
+    qa.nr = nr;
+    qa.na = na;
+    qa.grp = pl->grp;
+    qa.pair_tgt = pl->pair_tgt;
+    qa.pair_patch = pl->pair_patch;
+    qa.pair_off = pl->pair_off;
+    qa.coef = pl->coef;
+    qa.tau = pl->tau;
+    qa.val = (double *)val;
+    qa.stack = pl->stack;
+    qa.flags = pl->flags;
+    qa.stats = pl->stats;
+    for (int d = 1; d <= 8; ++d) {
+        const int64_t ns = pl->seg_start_h[d], nc = pl->seg_len_h[d];
+        const int64_t ss = pl->seg_start_h[9 + d], sc = pl->seg_len_h[9 + d];
+        if (nc + sc == 0) continue;
+        if (cplx) launch_degree<true>(d, pl, qa, ns, nc, ss, sc, st, tm);
+        else launch_degree<false>(d, pl, qa, ns, nc, ss, sc, st, tm);
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    if (stats) {
+        int hflags[kNumFlags];
+        unsigned long long hs[kNumStats];
+        HIP_TRY(ctx, hipMemcpyAsync(hflags, pl->flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipMemcpyAsync(hs, pl->stats, sizeof(hs), hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
+        stats->near_pairs = (int64_t)hs[kStatNear];
+        stats->self_pairs = (int64_t)hs[kStatSelf];
+        stats->visits = (int64_t)hs[kStatVisits];
+        stats->checks = (int64_t)hs[kStatChecks];
+        stats->nonconverged = (int64_t)hs[kStatNonconv];
+        stats->max_level = (int64_t)hs[kStatMaxLevel];
+        stats->ms_builder = tm.on ? tm.total(kPhBuilder) : 0.0;
+        stats->ms_prep = tm.on ? tm.total(kPhPrep) : 0.0;
+        stats->ms_self = tm.on ? tm.total(kPhSelf) : 0.0;
+        stats->ms_near = tm.on ? tm.total(kPhNear) : 0.0;
+        stats->ms_weights = tm.on ? tm.total(kPhWeights) : 0.0;
+        nfq_status fs = check_flags(ctx, hflags);
+        if (fs != NFQ_OK) return fs;
+        if (hs[kStatNonconv] > 0) return NFQ_WARN_NONCONVERGED;
+    }
+    return NFQ_OK;
+}
+
+nfq_status nfq_apply(nfq_plan *pl, const int32_t *col, const void *val, const void *sigma, void *y)
+{
+    if (!pl || !col || !val || !sigma || !y) return fail(pl ? pl->ctx : nullptr, NFQ_ERR_INVALID_ARG, "null argument");
+    nfq_ctx *ctx = pl->ctx;
+    if (pl->value_kind < 0) return fail(ctx, NFQ_ERR_INVALID_ARG, "nfq_apply before nfq_generate");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const int64_t NT = pl->pb.NT;
+    if (NT == 0) return NFQ_OK;
+    if (pl->value_kind == 1)
+        hipLaunchKernelGGL(k_apply<true>, dim3(nblk(NT, 4)), dim3(256), 0, ctx->stream, NT, pl->row_ptr,
+                           col, (const double *)val, (const double *)sigma, (double *)y);
+    else
+        hipLaunchKernelGGL(k_apply<false>, dim3(nblk(NT, 4)), dim3(256), 0, ctx->stream, NT, pl->row_ptr,
+                           col, (const double *)val, (const double *)sigma, (double *)y);
+    HIP_TRY(ctx, hipGetLastError());
+    return NFQ_OK;
+}
+
+nfq_status nfq_sync(nfq_ctx *ctx)
+{
+    if (!ctx) return NFQ_ERR_INVALID_ARG;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return NFQ_OK;
+}
+
+}  // extern "C"
