@@ -1,0 +1,147 @@
+#!/usr/bin/env python
+"""Benchmark of the near-field quadrature-correction generator on one GPU.
+
+One step = one nfq_generate call over the whole workload: pair/work-queue
+builder, patch preparation, self quadrature, adaptive near quadrature,
+moments -> node weights, column indices.  Inputs (patch nodes, targets, near
+lists) are resident in device memory before timing starts.
+
+Workload: Helmholtz combined field D - ik S, k = 2 pi, unit sphere with 1280
+quadratic patches at degree 4 (15 nodes, 19,200 on-surface targets), near
+radius 1.25 R_j, tol 1e-8, complex128.
+
+Prints one JSON line (see the field list at the end of main()).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "near-field target-points/s at tol 1e-8 (fwd; fwd+adjoint); % FP64 peak"
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector peak
+# flops per kernel evaluation of the combined field (add/mul = 1, fma = 2,
+# sqrt/div/sin/cos = 1), per moment of a complex-by-real MAC: 4
+C_KERNEL = {"laplace": 12, "laplace_cplx": 18, "helmholtz": 40}
+
+
+def kernel_flops(prob):
+    if prob.k != 0:
+        return C_KERNEL["helmholtz"]
+    return C_KERNEL["laplace"] if prob.real_kernel else C_KERNEL["laplace_cplx"]
+
+
+def cpu_baseline(prob, seconds):
+    """The oracle (method mode, one thread) on whole rows of randomly chosen
+    targets of the same workload, until `seconds` of CPU work are spent."""
+    import numpy as np
+    import oracle
+    run = oracle.OracleRun(prob, mode=oracle.METHOD)
+    rng = np.random.default_rng(2024)
+    order = rng.permutation(prob.NT)
+    done = 0
+    t0 = time.perf_counter()
+    for t in order:
+        own = int(np.searchsorted(prob.node_ptr, t, side="right") - 1)
+        for j in list(prob.near_patch[prob.near_row_ptr[t]:prob.near_row_ptr[t + 1]]) + [own]:
+            run.pair(int(t), int(j))
+        done += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "target-points/s", "cores": 1, "kind": "oracle",
+            "sample": "%d random targets of the same workload, full rows (near + self blocks), "
+                      "oracle method mode, one thread, %.1f s" % (done, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build measures the generator on a single "
+              "MI355X (the multi-GPU row sharding is described in DESIGN.md, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2006_02545_amd import nfq, surfaces
+
+    prob = surfaces.config(1)
+    torch.cuda.set_device(0)
+    ctx = nfq.Context(0)
+    plan = nfq.plan_for(ctx, prob)
+    col = torch.empty(plan.nnz, dtype=torch.int32, device="cuda")
+    val = torch.empty(plan.nnz, dtype=torch.complex128, device="cuda")
+    gen = dict(alpha=prob.alpha, beta=prob.beta, k=prob.k, tol=prob.tol, col=col, val=val)
+
+    for _ in range(args.warmup):
+        plan.generate(stats=False, **gen)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.generate(stats=False, **gen)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) / args.steps * 1e3
+    value = prob.NT / (ms * 1e-3)
+
+    # per-phase durations from HIP events recorded on the library's stream
+    phases = {k: 0.0 for k in ("ms_builder", "ms_prep", "ms_self", "ms_near", "ms_weights")}
+    st = None
+    nrep = max(1, min(args.steps, 5))
+    for _ in range(nrep):
+        _, _, st = plan.generate(stats=True, timing=True, **gen)
+        for k in phases:
+            phases[k] += st[k] / nrep
+    nd = (int(prob.degree[0]) + 1) * (int(prob.degree[0]) + 2) // 2
+    nq = 64
+    # algorithmic flops of the adaptive near kernel (dominant): every
+    # subtriangle visit of every pair evaluates the kernel at nq nodes and
+    # accumulates nd complex moments
+    flops_near = st["visits"] * nq * (kernel_flops(prob) + 4 * nd)
+    achieved = flops_near / (phases["ms_near"] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "k_near (adaptive near quadrature)",
+                "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "flops_per_launch": flops_near, "ms_per_launch": phases["ms_near"]}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "target-points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "complex128",
+        "data": "synthetic",
+        "config": {"workload": "cfie_sphere1280_d4", "patches": prob.P, "degree": int(prob.degree[0]),
+                   "targets": prob.NT, "near_pairs": int(prob.near_patch.size),
+                   "kernel": "D - ik S", "k": prob.k.real, "tol": prob.tol, "eta": prob.eta,
+                   "loosen": 1.0, "global_batch": prob.NT, "parallelism": "single-gpu"},
+        "fwd_adjoint": None,
+        "phase_ms": phases,
+        "gen_stats": {k: st[k] for k in ("near_pairs", "self_pairs", "visits", "checks",
+                                         "nonconverged", "max_level")},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -47,6 +47,7 @@
 #define IU _Complex_I
 
 typedef double complex cplx;
+typedef __float128 qreal;
 
 #define ORC_MAXD 12
 #define ORC_MAXND ((ORC_MAXD + 1) * (ORC_MAXD + 2) / 2)
@@ -610,48 +611,76 @@ static void gl_interval(vfun_t f, void *ctx, double a, double b, int nd, cplx *o
     }
 }
 
-typedef struct { double a, b; int depth; cplx I[ORC_MAXND]; } seg_t;
+typedef struct { double a, b; double err; cplx I[ORC_MAXND]; } seg_t;
 
-/* accept the two halves of [a,b] when || halves - whole || <= tol (b-a)
- * or <= rel_guard ||halves|| (guard against the rounding floor), or when
- * the halves are max_depth bisections deep.  The depth cap matters only
- * next to the self target, where n(y).(x - X(y)) = O(s^2) is formed from
- * O(s) factors and rounding dominates for s below ~1e-6; intervals there
- * carry a negligible share of the integral. */
-static void adapt1d(vfun_t f, void *ctx, double a, double b, double tol, double rel_guard,
-                    int max_depth, int nd, cplx *out, int64_t *nevals)
+/* Estimate on [a,b]: the sum of Gauss-Legendre on the two halves; its error
+ * estimate is the distance to Gauss-Legendre on the whole interval. */
+static void seg_eval(vfun_t f, void *ctx, double a, double b, int nd, const cplx *whole,
+                     seg_t *s, int64_t *nevals)
 {
-    int cap = 256, sp = 0;
-    seg_t *stk = malloc(sizeof(seg_t) * cap);
-    seg_t s0; s0.a = a; s0.b = b; s0.depth = 0;
-    gl_interval(f, ctx, a, b, nd, s0.I);
+    cplx L[ORC_MAXND], R[ORC_MAXND];
+    double m = 0.5 * (a + b);
+    gl_interval(f, ctx, a, m, nd, L);
+    gl_interval(f, ctx, m, b, nd, R);
+    *nevals += 40;
+    s->a = a; s->b = b;
+    for (int i = 0; i < nd; ++i) s->I[i] = L[i] + R[i];
+    s->err = cnorm_diff(nd, s->I, whole);
+}
+
+/* Globally adaptive 1-D integration (in the spirit of QUADPACK's QAG):
+ * keep a list of intervals with estimates and error estimates; split the
+ * interval with the largest error until the summed error is at most
+ * max(tol (b - a), rel_guard ||sum||) or max_iv intervals are in use.  The
+ * relative guard stops the refinement at the rounding floor of the
+ * integrand; the interval budget bounds the cost (next to the self target
+ * the double-layer numerator n(y).(x - X(y)) = O(s^2) is formed from O(s)
+ * factors and carries relative noise ~1e-19 / s^2). */
+static void adapt1d(vfun_t f, void *ctx, double a, double b, double tol, double rel_guard,
+                    int max_iv, int nd, cplx *out, int64_t *nevals)
+{
+    seg_t *iv = malloc(sizeof(seg_t) * max_iv);
+    cplx whole[ORC_MAXND];
+    gl_interval(f, ctx, a, b, nd, whole);
     *nevals += 20;
-    stk[sp++] = s0;
-    for (int i = 0; i < nd; ++i) out[i] = 0;
-    while (sp > 0) {
-        seg_t s = stk[--sp];
-        double m = 0.5 * (s.a + s.b);
-        seg_t L, R;
-        L.a = s.a; L.b = m; R.a = m; R.b = s.b;
-        L.depth = R.depth = s.depth + 1;
-        gl_interval(f, ctx, L.a, L.b, nd, L.I);
-        gl_interval(f, ctx, R.a, R.b, nd, R.I);
-        *nevals += 40;
+    seg_eval(f, ctx, a, b, nd, whole, &iv[0], nevals);
+    int n = 1;
+    for (;;) {
         cplx S[ORC_MAXND];
-        for (int i = 0; i < nd; ++i) S[i] = L.I[i] + R.I[i];
-        double err = cnorm_diff(nd, S, s.I);
-        double thr = tol * (s.b - s.a);
-        double g = rel_guard * cnorm(nd, S);   /* guard against the rounding floor */
-        if (g > thr) thr = g;
-        if (err <= thr || s.depth >= max_depth) {
-            for (int i = 0; i < nd; ++i) out[i] += S[i];
-        } else {
-            if (sp + 2 > cap) { cap *= 2; stk = realloc(stk, sizeof(seg_t) * cap); }
-            stk[sp++] = R;
-            stk[sp++] = L;
+        double E = 0.0;
+        int worst = 0;
+        for (int i = 0; i < nd; ++i) S[i] = 0;
+        for (int k = 0; k < n; ++k) {
+            for (int i = 0; i < nd; ++i) S[i] += iv[k].I[i];
+            E += iv[k].err;
+            if (iv[k].err > iv[worst].err) worst = k;
         }
+        double thr = tol * (b - a), g = rel_guard * cnorm(nd, S);
+        if (g > thr) thr = g;
+        if (E <= thr || n + 1 > max_iv) {
+            for (int i = 0; i < nd; ++i) out[i] = S[i];
+            break;
+        }
+        /* intervals below 1e-7 of the range are accepted as they are: their
+         * share of the integral is below the tolerances checked, while the
+         * integrand's rounding noise grows as they shrink towards the
+         * singular point */
+        if (iv[worst].b - iv[worst].a < 1e-7 * (b - a)) {
+            iv[worst].err = 0.0;
+            continue;
+        }
+        /* split the worst interval: its two halves become intervals */
+        seg_t w = iv[worst];
+        double m = 0.5 * (w.a + w.b);
+        cplx hl[ORC_MAXND], hr[ORC_MAXND];
+        gl_interval(f, ctx, w.a, m, nd, hl);
+        gl_interval(f, ctx, m, w.b, nd, hr);
+        *nevals += 40;
+        seg_eval(f, ctx, w.a, m, nd, hl, &iv[worst], nevals);
+        seg_eval(f, ctx, m, w.b, nd, hr, &iv[n], nevals);
+        ++n;
     }
-    free(stk);
+    free(iv);
 }
 
 /* Self quadrature: target at reference node t = (ut, vt) of its own
@@ -663,23 +692,99 @@ typedef struct {
     const patch_t *pt;
     const kern_t *kk;
     long double x[3];
+    qreal xq[3];
     double t[2], P0[2], P1[2], det;
     double lam;
     double tol_in;
     int64_t *nevals;
 } self_ctx;
 
+/* Quad-precision (__float128) chart position and normal for the self
+ * integrand: next to the target the double-layer numerator
+ * n(y).(X(t) - X(y)) = O(s^2) is formed from O(s) factors; in quad precision
+ * its rounding noise (~1e-34 / s^2) stays far below every tolerance the
+ * adaptive tests use. */
+static qreal ipowq_(qreal x, int e)
+{
+    if (e < 0) return 0;
+    qreal r = 1;
+    for (int i = 0; i < e; ++i) r *= x;
+    return r;
+}
+
+static void koorn_q(int d, qreal u, qreal v, qreal *K, qreal *Ku, qreal *Kv)
+{
+    for (int n = 0; n <= d; ++n)
+        for (int m = 0; m <= n; ++m) {
+            int k = n - m, b = 2 * m + 1;
+            qreal A = 0, Av = 0;
+            for (int s = 0; s <= k; ++s) {
+                qreal c = (qreal)binom(k, k - s) * (qreal)binom(k + b, s);
+                A += c * ipowq_(-v, s) * ipowq_(1 - v, k - s);
+                Av += c * (-(qreal)s * ipowq_(-v, s - 1) * ipowq_(1 - v, k - s)
+                           - (qreal)(k - s) * ipowq_(-v, s) * ipowq_(1 - v, k - s - 1));
+            }
+            qreal B = 0, Bu = 0, Bv = 0, w = u + v - 1;
+            for (int s = 0; s <= m; ++s) {
+                qreal c = (qreal)binom(m, s) * (qreal)binom(m, s);
+                B += c * ipowq_(w, s) * ipowq_(u, m - s);
+                Bu += c * ((qreal)s * ipowq_(w, s - 1) * ipowq_(u, m - s)
+                           + (qreal)(m - s) * ipowq_(w, s) * ipowq_(u, m - s - 1));
+                Bv += c * (qreal)s * ipowq_(w, s - 1) * ipowq_(u, m - s);
+            }
+            /* c_nm = sqrt(2(n+1)(2m+1)) to quad precision: long double
+             * square root refined by one Newton step */
+            qreal c2 = (qreal)(2 * (n + 1) * (2 * m + 1));
+            qreal cn = (qreal)sqrtl((long double)c2);
+            cn = 0.5 * (cn + c2 / cn);
+            int idx = n * (n + 1) / 2 + m;
+            K[idx] = cn * A * B;
+            Ku[idx] = cn * A * Bu;
+            Kv[idx] = cn * (Av * B + A * Bv);
+        }
+}
+
+/* X(u,v) and n = X_u x X_v in quad precision, u = ut + s*du etc. formed in
+ * quad precision as well. */
+static void chart_q(const patch_t *pt, qreal u, qreal v, qreal X[3], qreal n[3])
+{
+    qreal K[ORC_MAXND], Ku[ORC_MAXND], Kv[ORC_MAXND], Xu[3], Xv[3];
+    koorn_q(pt->d, u, v, K, Ku, Kv);
+    for (int c = 0; c < 3; ++c) {
+        qreal a = 0, au = 0, av = 0;
+        for (int i = 0; i < pt->nd; ++i) {
+            qreal cf = (qreal)pt->coef[c][i];
+            a += cf * K[i];
+            au += cf * Ku[i];
+            av += cf * Kv[i];
+        }
+        X[c] = a; Xu[c] = au; Xv[c] = av;
+    }
+    n[0] = Xu[1] * Xv[2] - Xu[2] * Xv[1];
+    n[1] = Xu[2] * Xv[0] - Xu[0] * Xv[2];
+    n[2] = Xu[0] * Xv[1] - Xu[1] * Xv[0];
+}
+
 static void self_inner(double s, void *vctx, cplx *out)
 {
     self_ctx *c = (self_ctx *)vctx;
     const patch_t *pt = c->pt;
-    double ex = c->P0[0] + c->lam * (c->P1[0] - c->P0[0]) - c->t[0];
-    double ey = c->P0[1] + c->lam * (c->P1[1] - c->P0[1]) - c->t[1];
-    double u = c->t[0] + s * ex, v = c->t[1] + s * ey;
+    qreal ex = (qreal)c->P0[0] + (qreal)c->lam * ((qreal)c->P1[0] - c->P0[0]) - c->t[0];
+    qreal ey = (qreal)c->P0[1] + (qreal)c->lam * ((qreal)c->P1[1] - c->P0[1]) - c->t[1];
+    qreal uq = (qreal)c->t[0] + (qreal)s * ex, vq = (qreal)c->t[1] + (qreal)s * ey;
+    qreal X[3], n[3];
+    chart_q(pt, uq, vq, X, n);
+    qreal dl[3] = {c->xq[0] - X[0], c->xq[1] - X[1], c->xq[2] - X[2]};
+    double r = (double)sqrtl((long double)(dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2]));
+    double ndx = (double)(n[0] * dl[0] + n[1] * dl[1] + n[2] * dl[2]);
+    double J = (double)sqrtl((long double)(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]));
+    const kern_t *kk = c->kk;
+    cplx e = cexp(IU * kk->k * r);
+    cplx G = e / (4.0 * ORC_PI * r);
+    cplx D = ndx * (1.0 - IU * kk->k * r) * e / (4.0 * ORC_PI * r * r * r);
+    cplx f = (kk->alpha * G * J + kk->beta * D) * s * c->det;
     double K[ORC_MAXND];
-    geo_t g;
-    chart(pt, u, v, &g, K);
-    cplx f = kernel_val(c->kk, c->x, &g) * s * c->det;
+    orc_koornwinder(pt->d, (double)uq, (double)vq, K, NULL, NULL);
     for (int i = 0; i < pt->nd; ++i) out[i] = f * K[i];
 }
 
@@ -687,9 +792,7 @@ static void self_outer(double lam, void *vctx, cplx *out)
 {
     self_ctx *c = (self_ctx *)vctx;
     c->lam = lam;
-    /* inner integrands carry relative noise up to ~2e-18/s^2 (the O(s^2)
-     * double-layer numerator): guard 1e-12 */
-    adapt1d(self_inner, c, 0.0, 1.0, c->tol_in, 1e-12, 16, c->pt->nd, out, c->nevals);
+    adapt1d(self_inner, c, 0.0, 1.0, c->tol_in, 1e-12, 60, c->pt->nd, out, c->nevals);
 }
 
 /* The self target is the chart point X(u_t, v_t) itself (it equals the
@@ -709,6 +812,11 @@ static void self_moments(const patch_t *pt, const kern_t *kk, double ut, double 
         self_ctx c;
         c.pt = pt; c.kk = kk;
         for (int q = 0; q < 3; ++q) c.x[q] = x[q];
+        {
+            qreal Xq[3], nq[3];
+            chart_q(pt, (qreal)ut, (qreal)vt, Xq, nq);
+            for (int q = 0; q < 3; ++q) c.xq[q] = Xq[q];
+        }
         c.t[0] = ut; c.t[1] = vt;
         c.P0[0] = V[e][0]; c.P0[1] = V[e][1];
         c.P1[0] = V[(e + 1) % 3][0]; c.P1[1] = V[(e + 1) % 3][1];
@@ -718,8 +826,8 @@ static void self_moments(const patch_t *pt, const kern_t *kk, double ut, double 
         c.tol_in = tau / 3.0 * 0.1;
         c.nevals = &st->self_evals;
         cplx part[ORC_MAXND];
-        /* the outer integrand inherits the inner guard as noise: guard 1e-11 */
-        adapt1d(self_outer, &c, 0.0, 1.0, tau / 3.0, 1e-11, 14, nd, part, &st->self_evals);
+        /* the outer integrand inherits the inner accuracy as noise */
+        adapt1d(self_outer, &c, 0.0, 1.0, tau / 3.0, 1e-11, 80, nd, part, &st->self_evals);
         for (int i = 0; i < nd; ++i) tot[i] += part[i];
     }
     st->self_targets += 1;

@@ -84,9 +84,12 @@ struct Timer {
 
 namespace {
 
+thread_local std::string g_err;  // last error of a call that has no context
+
 nfq_status fail(nfq_ctx *ctx, nfq_status s, const std::string &msg)
 {
     if (ctx) ctx->err = msg;
+    else g_err = msg;
     return s;
 }
 
@@ -266,31 +269,28 @@ const char *nfq_status_str(nfq_status s)
     }
 }
 
-const char *nfq_last_error(nfq_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char *nfq_last_error(nfq_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
 
 nfq_status nfq_create(int device, void *hip_stream, nfq_ctx **out)
 {
-    if (!out) return NFQ_ERR_INVALID_ARG;
+    if (!out) return fail(nullptr, NFQ_ERR_INVALID_ARG, "null output pointer");
     *out = nullptr;
     nfq_ctx *ctx = new (std::nothrow) nfq_ctx;
-    if (!ctx) return NFQ_ERR_OUT_OF_MEMORY;
+    if (!ctx) return fail(nullptr, NFQ_ERR_OUT_OF_MEMORY, "context");
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
-    if (hipSetDevice(device) != hipSuccess) {
-        delete ctx;
-        return NFQ_ERR_HIP;
-    }
+    auto bail = [&](nfq_status s, const std::string &m) {
+        nfq_destroy(ctx);
+        return fail(nullptr, s, m);
+    };
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return bail(NFQ_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
     std::vector<double> rule;
     conical_rule(kNG, rule);
-    if (dalloc(&ctx->drule, rule.size()) != hipSuccess ||
-        hipMemcpy(ctx->drule, rule.data(), rule.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
-        delete ctx;
-        return NFQ_ERR_HIP;
-    }
-    if (ensure_self_rule(ctx, 10, 16) != NFQ_OK) {
-        delete ctx;
-        return NFQ_ERR_HIP;
-    }
+    e = dalloc(&ctx->drule, rule.size());
+    if (e == hipSuccess) e = hipMemcpy(ctx->drule, rule.data(), rule.size() * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(NFQ_ERR_HIP, std::string("rule upload: ") + hipGetErrorString(e));
+    if (ensure_self_rule(ctx, 10, 16) != NFQ_OK) return bail(NFQ_ERR_HIP, "self rule upload: " + ctx->err);
     *out = ctx;
     return NFQ_OK;
 }

@@ -131,8 +131,7 @@ class Context:
 
     def _check(self, st, h=None):
         if st < 0:
-            msg = self.L.nfq_last_error(h).decode() if h is not None else ""
-            raise NfqError(st, msg)
+            raise NfqError(st, self.L.nfq_last_error(h).decode())
         return st
 
     def register_degree(self, d, uv, w=None):
