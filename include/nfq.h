@@ -115,11 +115,15 @@ typedef struct {
     int32_t self_nr;
     int32_t self_na;
     int32_t flags;  /* bit 0 (NFQ_FLAG_TIMING): time each phase with HIP events
-                       on the context's stream; reported in nfq_stats */
+                       on the context's stream, reported in nfq_stats;
+                       bit 1 (NFQ_FLAG_PER_PAIR): use the plain per-pair near
+                       kernel (one wavefront per pair, no reuse of subtriangle
+                       geometry across targets) instead of the patch-centric one */
     int32_t pad;
 } nfq_params;
 
 #define NFQ_FLAG_TIMING 1
+#define NFQ_FLAG_PER_PAIR 2
 
 typedef struct {
     int64_t near_pairs;

@@ -520,8 +520,23 @@ static double cnorm(int nd, const cplx *a)
 typedef struct {
     double tri[6];
     int depth;
+    uint64_t code;   /* path in the quadtree: child indices in base 4 */
     cplx I[ORC_MAXND];
 } node_t;
+
+/* optional trace of the checked triangles ((depth << 56) | code), for tests
+ * that study the shape of the subdivision trees */
+static uint64_t *g_trace = NULL;
+static int64_t g_trace_cap = 0, g_trace_n = 0;
+
+void orc_set_trace(uint64_t *buf, int64_t cap)
+{
+    g_trace = buf;
+    g_trace_cap = cap;
+    g_trace_n = 0;
+}
+
+int64_t orc_trace_count(void) { return g_trace_n; }
 
 static int near_moments(const patch_t *pt, const kern_t *kk, const long double x[3], double tau,
                         const double *rule, int nq, int max_depth, int truth, cplx *tot,
@@ -531,7 +546,7 @@ static int near_moments(const patch_t *pt, const kern_t *kk, const long double x
     int cap = 1024;
     node_t *stk = malloc(sizeof(node_t) * cap);
     int sp = 0;
-    node_t root = {{0, 0, 1, 0, 0, 1}, 0, {0}};
+    node_t root = {{0, 0, 1, 0, 0, 1}, 0, 0, {0}};
     tri_moments(pt, kk, x, root.tri, rule, nq, root.I);
     st->visits += 1;
     stk[sp++] = root;
@@ -539,6 +554,8 @@ static int near_moments(const patch_t *pt, const kern_t *kk, const long double x
     int nonconv = 0;
     while (sp > 0) {
         node_t T = stk[--sp];
+        if (g_trace && g_trace_n < g_trace_cap)
+            g_trace[g_trace_n++] = ((uint64_t)T.depth << 56) | T.code;
         double a[2] = {T.tri[0], T.tri[1]}, b[2] = {T.tri[2], T.tri[3]}, c[2] = {T.tri[4], T.tri[5]};
         double ab[2] = {0.5 * (a[0] + b[0]), 0.5 * (a[1] + b[1])};
         double bc[2] = {0.5 * (b[0] + c[0]), 0.5 * (b[1] + c[1])};
@@ -554,6 +571,7 @@ static int near_moments(const patch_t *pt, const kern_t *kk, const long double x
         for (int k = 0; k < 4; ++k) {
             memcpy(ch[k].tri, tris[k], sizeof(tris[k]));
             ch[k].depth = T.depth + 1;
+            ch[k].code = T.code * 4 + (uint64_t)k;
             tri_moments(pt, kk, x, ch[k].tri, rule, nq, ch[k].I);
             for (int i = 0; i < nd; ++i) S[i] += ch[k].I[i];
         }

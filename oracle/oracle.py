@@ -79,6 +79,10 @@ def _bind(L):
     L.orc_apply.argtypes = [i64, vp, vp, vp, vp, vp]
     L.orc_patch_info.argtypes = [vp, i64, vp, vp]
     L.orc_chart.argtypes = [vp, i64, dbl, dbl, vp]
+    L.orc_set_trace.argtypes = [vp, i64]
+    L.orc_set_trace.restype = None
+    L.orc_trace_count.argtypes = []
+    L.orc_trace_count.restype = i64
 
 
 def _p(a):
@@ -189,6 +193,18 @@ class OracleRun:
         if rc:
             raise RuntimeError("orc_generate_rows rc=%d" % rc)
         return rp, col, val[0::2] + 1j * val[1::2]
+
+    def pair_trace(self, t, j, cap=1 << 20):
+        """Triangles checked by the adaptive scheme for pair (t, j):
+        array of (depth << 56) | path code."""
+        buf = np.zeros(cap, dtype=np.uint64)
+        lib().orc_set_trace(_p(buf), cap)
+        try:
+            self.pair(t, j)
+            n = lib().orc_trace_count()
+        finally:
+            lib().orc_set_trace(None, 0)
+        return buf[:n].copy()
 
     def patch_info(self, j):
         dj, nv = np.zeros(1), np.zeros(1)

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "fastmath.hpp"
 #include "koorn.hpp"
 
 namespace nfq {
@@ -47,7 +48,7 @@ __device__ __forceinline__ void kern_eval(const Kern &k, bool helm, const double
     const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (r2 == 0.0) singular = 1;
-    const double rinv = 1.0 / __builtin_sqrt(r2);
+    const double rinv = rsqrt_nr(r2);
     const double J = __builtin_sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
     const double nd = n[0] * dx + n[1] * dy + n[2] * dz;
     const double g0 = kInv4Pi * rinv;            // 1/(4 pi r)
@@ -60,7 +61,7 @@ __device__ __forceinline__ void kern_eval(const Kern &k, bool helm, const double
     }
     const double r = r2 * rinv;
     double s, c;
-    sincos(k.kr * r, &s, &c);
+    sincos_cw(k.kr * r, &s, &c);
     if (k.ki != 0.0) {
         const double damp = exp(-k.ki * r);
         s *= damp;

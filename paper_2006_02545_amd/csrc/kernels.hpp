@@ -215,17 +215,29 @@ __global__ void k_pairs(Problem pb, const int64_t *row_ptr, const int64_t *pair_
     }
 }
 
-// Scatter pairs into their (degree, kind) segment.
-__global__ void k_group(int64_t np, const int32_t *pair_patch, const int8_t *pair_self,
-                        const int32_t *degree, const int64_t *seg_start, unsigned long long *cursor,
-                        int32_t *grp)
+// Scatter pairs into their (degree, kind) segment: slots are counted per
+// block in LDS and reserved with one global atomic per (block, key).
+__global__ __launch_bounds__(256) void k_group(int64_t np, const int32_t *pair_patch,
+                                               const int8_t *pair_self, const int32_t *degree,
+                                               const int64_t *seg_start,
+                                               unsigned long long *cursor, int32_t *grp)
 {
+    __shared__ unsigned int s_cnt[18];
+    __shared__ unsigned long long s_base[18];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    const int d = degree[pair_patch[p]];
-    const int key = (pair_self[p] ? 9 : 0) + d;
-    const unsigned long long slot = atomicAdd(&cursor[key], 1ull);
-    grp[seg_start[key] + (int64_t)slot] = (int32_t)p;
+    if (threadIdx.x < 18) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int key = -1;
+    unsigned int local = 0;
+    if (p < np) {
+        key = (pair_self[p] ? 9 : 0) + degree[pair_patch[p]];
+        local = atomicAdd(&s_cnt[key], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 18 && s_cnt[threadIdx.x] > 0)
+        s_base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], (unsigned long long)s_cnt[threadIdx.x]);
+    __syncthreads();
+    if (key >= 0) grp[seg_start[key] + (int64_t)(s_base[key] + local)] = (int32_t)p;
 }
 
 // ---------------------------------------------------------- patch prep
@@ -540,15 +552,27 @@ __global__ __launch_bounds__((64 * QuadShape<D, CPLX>::WPB)) void k_near(QuadArg
 // -------------------------------------------------------- self quadrature
 
 template <int D, bool CPLX>
-__global__ __launch_bounds__((64 * QuadShape<D, CPLX>::WPB)) void k_self(QuadArgs a)
+struct SelfShape {
+    static constexpr int ND = nd_of(D);
+    static constexpr int NV = CPLX ? 2 * ND : ND;
+    static constexpr int RP = (ND + 2) | 1;   // LDS row pitch: K[ND], f_re w, f_im w
+    static constexpr int WPB = 2;
+};
+
+// Self quadrature.  One wavefront per target; the target-split rule's nodes
+// are taken 64 at a time (one per lane): each lane evaluates chart, kernel and
+// basis at its node and stages K and the weighted kernel value in LDS; then
+// lane v accumulates component v of the moments over the 64 staged nodes.
+// No per-lane moment vector is kept in registers.
+template <int D, bool CPLX>
+__global__ __launch_bounds__((64 * SelfShape<D, CPLX>::WPB)) void k_self(QuadArgs a)
 {
-    using S = QuadShape<D, CPLX>;
-    constexpr int ND = S::ND, NV = S::NV, NVP = S::NVP, WPB = S::WPB;
-    __shared__ double s_red[WPB][64 * NVP];
-    __shared__ double s_out[WPB][NV];
+    using S = SelfShape<D, CPLX>;
+    constexpr int ND = S::ND, NV = S::NV, RP = S::RP, WPB = S::WPB;
+    constexpr int NL = (NV + 63) / 64;
+    __shared__ double s_stage[WPB][64 * RP];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    double *red = s_red[wv];
-    double *out = s_out[wv];
+    double *stage = s_stage[wv];
     const int64_t wave_id = (int64_t)blockIdx.x * WPB + wv;
     const int64_t nwaves = (int64_t)gridDim.x * WPB;
     const int nr = a.nr, na = a.na;
@@ -573,10 +597,11 @@ __global__ __launch_bounds__((64 * QuadShape<D, CPLX>::WPB)) void k_self(QuadArg
             G01 = Xu[0] * Xv[0] + Xu[1] * Xv[1] + Xu[2] * Xv[2];
             G11 = Xv[0] * Xv[0] + Xv[1] * Xv[1] + Xv[2] * Xv[2];
         }
-        // panels: for each edge (P_e, P_e+1) of T0, the triangle (t, P_e, P_e+1)
+        // panels: for each edge (P_e, P_e+1) of T0 the triangle (t, P_e, P_e+1)
         // is collapsed at t: y = t + s (A + lam E - t).  In the metric G the
         // distance from t to the edge point is sqrt(h^2 + (lam - mu)^2 L^2);
-        // lam = mu + (h/L) sinh(xi) makes the angular integrand smooth.
+        // lam = mu + (h/L) sinh(xi) makes the angular integrand smooth.  The
+        // panel is split at the foot (xi = 0) when it lies inside the edge.
         double pA[6][2], pE[6][2], pmu[6], phl[6], pdet[6], pxa[6], pxb[6];
         int npan = 0;
         const double Pv[3][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}};
@@ -592,57 +617,83 @@ __global__ __launch_bounds__((64 * QuadShape<D, CPLX>::WPB)) void k_self(QuadArg
             const double h = __builtin_sqrt(G00 * fx * fx + 2.0 * G01 * fx * fy + G11 * fy * fy);
             const double det = __builtin_fabs((Ax - tu) * Ey - (Ay - tv) * Ex);
             const double x0 = asinh(-mu * L / h), x1 = asinh((1.0 - mu) * L / h);
-            if (mu > 0.0 && mu < 1.0) {
+            const bool split = mu > 0.0 && mu < 1.0;
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                if (half == 1 && !split) break;
                 pA[npan][0] = Ax; pA[npan][1] = Ay; pE[npan][0] = Ex; pE[npan][1] = Ey;
-                pmu[npan] = mu; phl[npan] = h / L; pdet[npan] = det; pxa[npan] = x0; pxb[npan] = 0.0;
-                ++npan;
-                pA[npan][0] = Ax; pA[npan][1] = Ay; pE[npan][0] = Ex; pE[npan][1] = Ey;
-                pmu[npan] = mu; phl[npan] = h / L; pdet[npan] = det; pxa[npan] = 0.0; pxb[npan] = x1;
-                ++npan;
-            } else {
-                pA[npan][0] = Ax; pA[npan][1] = Ay; pE[npan][0] = Ex; pE[npan][1] = Ey;
-                pmu[npan] = mu; phl[npan] = h / L; pdet[npan] = det; pxa[npan] = x0; pxb[npan] = x1;
+                pmu[npan] = mu; phl[npan] = h / L; pdet[npan] = det;
+                pxa[npan] = split ? (half == 0 ? x0 : 0.0) : x0;
+                pxb[npan] = split ? (half == 0 ? 0.0 : x1) : x1;
                 ++npan;
             }
         }
-        double acc[NV];
+        double acc[NL];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+        for (int k = 0; k < NL; ++k) acc[k] = 0.0;
         const int per_panel = na * nr;
         const int total = npan * per_panel;
-        for (int q = lane; q < total; q += 64) {
-            const int pi = q / per_panel;
-            const int rem = q - pi * per_panel;
-            const int ia = rem / nr, ir = rem - ia * nr;
-            // select panel pi without dynamic register indexing
-            double Ax = 0, Ay = 0, Ex = 0, Ey = 0, mu = 0, hl = 0, det = 0, xa = 0, xb = 0;
+        for (int base = 0; base < total; base += 64) {
+            const int q = base + lane;
+            double fr = 0.0, fi = 0.0;
+            double K[ND];
 #pragma unroll
-            for (int k = 0; k < 6; ++k)
-                if (k == pi) {
-                    Ax = pA[k][0]; Ay = pA[k][1]; Ex = pE[k][0]; Ey = pE[k][1]; mu = pmu[k];
-                    hl = phl[k]; det = pdet[k]; xa = pxa[k]; xb = pxb[k];
+            for (int m = 0; m < ND; ++m) K[m] = 0.0;
+            if (q < total) {
+                const int pi = q / per_panel;
+                const int rem = q - pi * per_panel;
+                const int ia = rem / nr, ir = rem - ia * nr;
+                double Ax = 0, Ay = 0, Ex = 0, Ey = 0, mu = 0, hl = 0, det = 0, xa = 0, xb = 0;
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    if (k == pi) {
+                        Ax = pA[k][0]; Ay = pA[k][1]; Ex = pE[k][0]; Ey = pE[k][1]; mu = pmu[k];
+                        hl = phl[k]; det = pdet[k]; xa = pxa[k]; xb = pxb[k];
+                    }
+                const double xi = xa + (xb - xa) * a.gla[2 * ia];
+                const double lam = mu + hl * sinh(xi);
+                const double dlam = hl * cosh(xi) * (xb - xa) * a.gla[2 * ia + 1];
+                const double s = a.glr[2 * ir], ws = a.glr[2 * ir + 1];
+                const double dx = Ax + lam * Ex - tu, dy = Ay + lam * Ey - tv;
+                double X[3], Xu[3], Xv[3];
+                chart_eval<D>(cf, tu + s * dx, tv + s * dy, K, X, Xu, Xv);
+                const double n[3] = {Xu[1] * Xv[2] - Xu[2] * Xv[1], Xu[2] * Xv[0] - Xu[0] * Xv[2],
+                                     Xu[0] * Xv[1] - Xu[1] * Xv[0]};
+                kern_eval(a.kern, a.helm, x, X, n, fr, fi, singular);
+                const double w = s * det * ws * dlam;
+                fr *= w;
+                fi *= w;
+            }
+            double *row = stage + lane * RP;
+#pragma unroll
+            for (int m = 0; m < ND; ++m) row[m] = K[m];
+            row[ND] = fr;
+            row[ND + 1] = fi;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                const int v = lane + 64 * k;
+                if (v < NV) {
+                    const int m = CPLX ? (v >> 1) : v;
+                    const int part = CPLX ? (v & 1) : 0;
+                    double sacc = acc[k];
+                    for (int i = 0; i < 64; ++i)
+                        sacc = __builtin_fma(stage[i * RP + ND + part], stage[i * RP + m], sacc);
+                    acc[k] = sacc;
                 }
-            const double xi = xa + (xb - xa) * a.gla[2 * ia];
-            double sh, ch;
-            sh = sinh(xi);
-            ch = cosh(xi);
-            const double lam = mu + hl * sh;
-            const double dlam = hl * ch * (xb - xa) * a.gla[2 * ia + 1];
-            const double s = a.glr[2 * ir], ws = a.glr[2 * ir + 1];
-            const double dx = Ax + lam * Ex - tu, dy = Ay + lam * Ey - tv;
-            const double u = tu + s * dx, v = tv + s * dy;
-            double K[ND], X[3], Xu[3], Xv[3];
-            chart_eval<D>(cf, u, v, K, X, Xu, Xv);
-            const double n[3] = {Xu[1] * Xv[2] - Xu[2] * Xv[1], Xu[2] * Xv[0] - Xu[0] * Xv[2],
-                                 Xu[0] * Xv[1] - Xu[1] * Xv[0]};
-            double fr, fi;
-            kern_eval(a.kern, a.helm, x, X, n, fr, fi, singular);
-            const double w = s * det * ws * dlam;
-            acc_products<ND, CPLX>(acc, K, fr * w, fi * w);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        lds_group_reduce<NV, NVP, 64>(red, out, acc, lane);
         const int64_t off = a.pair_off[p];
-        for (int v = lane; v < NV; v += 64) a.val[(CPLX ? 2 : 1) * off + v] = out[v];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int v = lane + 64 * k;
+            if (v < NV) a.val[(CPLX ? 2 : 1) * off + v] = acc[k];
+        }
     }
     singular = wave_or(singular);
     if (lane == 0) {

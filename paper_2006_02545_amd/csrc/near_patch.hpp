@@ -1,0 +1,413 @@
+// near_patch.hpp -- patch-centric adaptive near quadrature (Section 4.3 of
+// the paper, with its reuse of subtriangle geometry across targets).
+//
+// One workgroup (4 wavefronts) owns one work item: a patch and up to 64 of
+// the targets in its near field.  It walks the union of the targets'
+// subdivision trees depth first.  A tree node ("group") is a subtriangle T
+// of T0 together with the set of targets (a 64-bit mask) whose test on T is
+// pending.  For a group the workgroup
+//   1. evaluates the chart at the 4 x 64 rule nodes of T's four children
+//      once (256 threads, one node each) and keeps position, weighted normal,
+//      weighted Jacobian and Koornwinder values in LDS;
+//   2. lets every wavefront take targets of the mask in turn: 16 lanes per
+//      child, 4 nodes per lane, kernel values times basis values accumulated
+//      in registers, then a 16-lane reduce-scatter (shuffles) that leaves
+//      every lane with a few components of the child's moments;
+//   3. applies the test ||I_T - sum I_C|| <= tau |T|/|T0|: a target that
+//      passes adds sum I_C to its output block; a failing target stores its
+//      four child moment vectors for the next level and joins the children's
+//      mask.
+// Output blocks are accumulated in depth-first order with one wavefront per
+// target and group, so the result does not depend on scheduling.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace nfq {
+
+constexpr int kGroupStack = 3 * kMaxDepth + 8;
+
+template <int D, bool CPLX>
+struct PatchShape {
+    static constexpr int ND = nd_of(D);
+    static constexpr int NV = CPLX ? 2 * ND : ND;
+    static constexpr int W = (NV + 15) / 16 * 16;   // padded components
+    static constexpr int PL = W / 16;                // components per lane after the reduce-scatter
+    static constexpr int GS = (7 + ND) | 1;          // LDS doubles per node (odd pitch)
+};
+
+struct PatchArgs {
+    Problem pb;
+    DegTab tab;
+    Kern kern;
+    int helm;
+    int max_depth;
+    const double *rule;       // [64][3]
+    const int32_t *items;     // [n][3]: patch, start in plist, count (<= 64)
+    int64_t item_seg, item_count;
+    const int32_t *plist;     // near pairs in patch-major order
+    const int32_t *pair_tgt;
+    const int64_t *pair_off;
+    const double *coef;
+    const double *tau;
+    double *val;
+    double *mom;              // per workgroup slot: [max_depth + 1][4][64][W]
+    int64_t mom_slot;         // doubles per slot
+    int *flags;
+    unsigned long long *stats;
+};
+
+// 16-lane reduce-scatter: on entry acc[W] holds this lane's partial sums;
+// on exit acc[0..PL) holds components [PL * (lane & 15), PL * (lane & 15) + PL)
+// summed over the 16 lanes of the lane's group.
+template <int W>
+__device__ __forceinline__ void reduce_scatter16(double *acc, int lane)
+{
+#pragma unroll
+    for (int step = 0; step < 4; ++step) {
+        const int m = 8 >> step;
+        const int w = W >> (step + 1);
+        const bool hi = (lane & m) != 0;
+#pragma unroll
+        for (int i = 0; i < w; ++i) {
+            const double lo_v = acc[i], hi_v = acc[i + w];
+            const double send = hi ? lo_v : hi_v;
+            const double keep = hi ? hi_v : lo_v;
+            acc[i] = keep + __shfl_xor(send, m, 64);
+        }
+    }
+}
+
+// Geometry of one rule node of triangle (A, B, C) into LDS: y, n w, J w, K.
+template <int D>
+__device__ __forceinline__ void node_geometry(const double *cf, double Ax, double Ay, double Bx,
+                                              double By, double Cx, double Cy, double ru, double rv,
+                                              double wgt, double *g)
+{
+    constexpr int ND = nd_of(D);
+    const double u = Ax + ru * (Bx - Ax) + rv * (Cx - Ax);
+    const double v = Ay + ru * (By - Ay) + rv * (Cy - Ay);
+    double K[ND], X[3], Xu[3], Xv[3];
+    chart_eval<D>(cf, u, v, K, X, Xu, Xv);
+    const double n0 = Xu[1] * Xv[2] - Xu[2] * Xv[1];
+    const double n1 = Xu[2] * Xv[0] - Xu[0] * Xv[2];
+    const double n2 = Xu[0] * Xv[1] - Xu[1] * Xv[0];
+    g[0] = X[0]; g[1] = X[1]; g[2] = X[2];
+    g[3] = n0 * wgt; g[4] = n1 * wgt; g[5] = n2 * wgt;
+    g[6] = __builtin_sqrt(n0 * n0 + n1 * n1 + n2 * n2) * wgt;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) g[7 + a] = K[a];
+}
+
+// Weighted kernel value at a node whose geometry g carries n w and J w.
+__device__ __forceinline__ void kern_node(const Kern &k, bool helm, const double x[3],
+                                          const double *g, double &fr, double &fi, int &singular)
+{
+    const double dx = x[0] - g[0], dy = x[1] - g[1], dz = x[2] - g[2];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 == 0.0) singular = 1;
+    const double rinv = rsqrt_nr(r2);
+    const double g0 = kInv4Pi * rinv;
+    const double gJ = g0 * g[6];
+    const double d0 = g0 * (g[3] * dx + g[4] * dy + g[5] * dz) * rinv * rinv;
+    if (!helm) {
+        fr = k.ar * gJ + k.br * d0;
+        fi = k.ai * gJ + k.bi * d0;
+        return;
+    }
+    const double r = r2 * rinv;
+    double s, c;
+    sincos_cw(k.kr * r, &s, &c);
+    if (k.ki != 0.0) {
+        const double damp = exp(-k.ki * r);
+        s *= damp;
+        c *= damp;
+    }
+    const double pr = 1.0 + k.ki * r, pi = -k.kr * r;
+    const double gr = gJ * c, gi = gJ * s;
+    const double qr = d0 * (pr * c - pi * s), qi = d0 * (pr * s + pi * c);
+    fr = k.ar * gr - k.ai * gi + k.br * qr - k.bi * qi;
+    fi = k.ar * gi + k.ai * gr + k.br * qi + k.bi * qr;
+}
+
+struct GroupEntry {
+    double tri[6];
+    int level;
+    int child;
+    unsigned long long mask;
+};
+
+template <int D, bool CPLX>
+__global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs a)
+{
+    using S = PatchShape<D, CPLX>;
+    constexpr int ND = S::ND, NV = S::NV, W = S::W, PL = S::PL, GS = S::GS;
+    constexpr int C = CPLX ? 2 : 1;
+    __shared__ double s_geo[256 * GS];
+    __shared__ GroupEntry s_stack[kGroupStack];
+    __shared__ double s_x[64][3];
+    __shared__ int64_t s_off[64];
+    __shared__ unsigned long long s_fail;
+    __shared__ int s_sp;
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int grp16 = lane >> 4, l16 = lane & 15;
+    double *mom = a.mom + (int64_t)blockIdx.x * a.mom_slot;
+    // moments of target slot s, child c at level L: mom[((L * 4 + c) * 64 + s) * W + comp]
+    auto mptr = [&](int L, int c, int s) { return mom + ((int64_t)(L * 4 + c) * 64 + s) * W; };
+    unsigned long long st_visits = 0, st_checks = 0, st_nonconv = 0, st_maxlev = 0, st_pairs = 0;
+    int singular = 0;
+
+    for (int64_t it = blockIdx.x; it < a.item_count; it += gridDim.x) {
+        const int32_t *item = a.items + 3 * (a.item_seg + it);
+        const int j = item[0], start = item[1], count = item[2];
+        const double *cf = a.coef + 3 * a.pb.node_ptr[j];
+        const double tau = a.tau[j];
+        if (tid < count) {
+            const int p = a.plist[start + tid];
+            const int64_t t = a.pair_tgt[p];
+            s_x[tid][0] = a.pb.txyz[3 * t];
+            s_x[tid][1] = a.pb.txyz[3 * t + 1];
+            s_x[tid][2] = a.pb.txyz[3 * t + 2];
+            const int64_t off = a.pair_off[p];
+            s_off[tid] = off;
+            for (int v = 0; v < NV; ++v) a.val[C * off + v] = 0.0;
+        }
+        if (tid < 64) {
+            // root geometry: node tid of the rule on T0
+            node_geometry<D>(cf, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, a.rule[3 * tid], a.rule[3 * tid + 1],
+                             a.rule[3 * tid + 2], s_geo + tid * GS);
+        }
+        __syncthreads();
+        // root moments of every target: one node per lane
+        for (int s = wv; s < count; s += 4) {
+            const double x[3] = {s_x[s][0], s_x[s][1], s_x[s][2]};
+            double acc[W];
+#pragma unroll
+            for (int v = 0; v < W; ++v) acc[v] = 0.0;
+            const double *g = s_geo + lane * GS;
+            double fr, fi;
+            kern_node(a.kern, a.helm, x, g, fr, fi, singular);
+#pragma unroll
+            for (int m = 0; m < ND; ++m) {
+                const double k = g[7 + m];
+                if (CPLX) { acc[2 * m] = fr * k; acc[2 * m + 1] = fi * k; }
+                else acc[m] = fr * k;
+            }
+            reduce_scatter16<W>(acc, lane);
+#pragma unroll
+            for (int i = 0; i < PL; ++i) {
+                acc[i] += __shfl_xor(acc[i], 16, 64);
+                acc[i] += __shfl_xor(acc[i], 32, 64);
+            }
+            if (grp16 == 0) {
+                double *dst = mptr(0, 0, s);
+#pragma unroll
+                for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = acc[i];
+            }
+            ++st_pairs;
+            ++st_visits;
+        }
+        if (tid == 0) {
+            GroupEntry &e = s_stack[0];
+            e.tri[0] = 0.0; e.tri[1] = 0.0; e.tri[2] = 1.0; e.tri[3] = 0.0; e.tri[4] = 0.0; e.tri[5] = 1.0;
+            e.level = 0;
+            e.child = 0;
+            e.mask = count == 64 ? ~0ull : ((1ull << count) - 1ull);
+            s_sp = 1;
+        }
+        __syncthreads();
+        while (true) {
+            if (s_sp == 0) break;
+            const GroupEntry e = s_stack[s_sp - 1];
+            __syncthreads();
+            if (tid == 0) {
+                s_sp = s_sp - 1;
+                s_fail = 0ull;
+            }
+            // children geometry: thread tid -> child tid / 64, node tid % 64
+            const double ax = e.tri[0], ay = e.tri[1], bx = e.tri[2], by = e.tri[3];
+            const double cx = e.tri[4], cy = e.tri[5];
+            const double abx = 0.5 * (ax + bx), aby = 0.5 * (ay + by);
+            const double bcx = 0.5 * (bx + cx), bcy = 0.5 * (by + cy);
+            const double cax = 0.5 * (cx + ax), cay = 0.5 * (cy + ay);
+            {
+                const int c = tid >> 6, q = tid & 63;
+                double Ax, Ay, Bx, By, Cx, Cy;
+                if (c == 0) { Ax = ax; Ay = ay; Bx = abx; By = aby; Cx = cax; Cy = cay; }
+                else if (c == 1) { Ax = abx; Ay = aby; Bx = bx; By = by; Cx = bcx; Cy = bcy; }
+                else if (c == 2) { Ax = cax; Ay = cay; Bx = bcx; By = bcy; Cx = cx; Cy = cy; }
+                else { Ax = bcx; Ay = bcy; Bx = cax; By = cay; Cx = abx; Cy = aby; }
+                const double area = __builtin_ldexp(1.0, -2 * (e.level + 1));
+                node_geometry<D>(cf, Ax, Ay, Bx, By, Cx, Cy, a.rule[3 * q], a.rule[3 * q + 1],
+                                 a.rule[3 * q + 2] * area, s_geo + tid * GS);
+            }
+            __syncthreads();
+            const double thr = tau * __builtin_ldexp(1.0, -2 * e.level);
+            const int L = e.level;
+            // targets of the mask, the k-th set bit to wavefront k % 4
+            unsigned long long mk = e.mask;
+            int k = 0;
+            while (mk) {
+                const int s = __builtin_ctzll(mk);
+                mk &= mk - 1ull;
+                if ((k++ & 3) != wv) continue;
+                const double x[3] = {s_x[s][0], s_x[s][1], s_x[s][2]};
+                double acc[W];
+#pragma unroll
+                for (int v = 0; v < W; ++v) acc[v] = 0.0;
+#pragma unroll 1
+                for (int i = 0; i < 4; ++i) {
+                    const double *g = s_geo + (grp16 * 64 + l16 + 16 * i) * GS;
+                    double fr, fi;
+                    kern_node(a.kern, a.helm, x, g, fr, fi, singular);
+#pragma unroll
+                    for (int m = 0; m < ND; ++m) {
+                        const double kv = g[7 + m];
+                        if (CPLX) {
+                            acc[2 * m] = __builtin_fma(fr, kv, acc[2 * m]);
+                            acc[2 * m + 1] = __builtin_fma(fi, kv, acc[2 * m + 1]);
+                        } else {
+                            acc[m] = __builtin_fma(fr, kv, acc[m]);
+                        }
+                    }
+                }
+                reduce_scatter16<W>(acc, lane);
+                // acc[0..PL): components of child grp16's moments; the sum
+                // over the four children by two more exchanges
+                double Ssum[PL], IT[PL];
+                const double *src = mptr(L, e.child, s);
+                double e2 = 0.0;
+#pragma unroll
+                for (int i = 0; i < PL; ++i) {
+                    double v = acc[i] + __shfl_xor(acc[i], 16, 64);
+                    v += __shfl_xor(v, 32, 64);
+                    Ssum[i] = v;
+                    IT[i] = src[PL * l16 + i];
+                    const double df = v - IT[i];
+                    e2 += grp16 == 0 ? df * df : 0.0;
+                }
+                const double err2 = wave_sum(e2);
+                ++st_checks;
+                st_visits += 4;
+                bool accept = err2 <= thr * thr;
+                if (!accept && L + 1 >= a.max_depth) {
+                    accept = true;
+                    ++st_nonconv;
+                }
+                if (accept) {
+                    if (grp16 == 0) {
+                        double *dst = a.val + C * s_off[s];
+#pragma unroll
+                        for (int i = 0; i < PL; ++i) {
+                            const int comp = PL * l16 + i;
+                            if (comp < NV) dst[comp] += Ssum[i];
+                        }
+                    }
+                    if ((unsigned long long)(L + 1) > st_maxlev) st_maxlev = L + 1;
+                } else {
+                    double *dst = mptr(L + 1, grp16, s);
+#pragma unroll
+                    for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = acc[i];
+                    if (lane == 0) atomicOr(&s_fail, 1ull << s);
+                }
+            }
+            __syncthreads();
+            if (tid == 0 && s_fail != 0ull) {
+                // push children 3..0 so that child 0 is processed next
+                for (int c = 3; c >= 0; --c) {
+                    GroupEntry &ne = s_stack[s_sp];
+                    double t0x, t0y, t1x, t1y, t2x, t2y;
+                    if (c == 0) { t0x = ax; t0y = ay; t1x = abx; t1y = aby; t2x = cax; t2y = cay; }
+                    else if (c == 1) { t0x = abx; t0y = aby; t1x = bx; t1y = by; t2x = bcx; t2y = bcy; }
+                    else if (c == 2) { t0x = cax; t0y = cay; t1x = bcx; t1y = bcy; t2x = cx; t2y = cy; }
+                    else { t0x = bcx; t0y = bcy; t1x = cax; t1y = cay; t2x = abx; t2y = aby; }
+                    ne.tri[0] = t0x; ne.tri[1] = t0y; ne.tri[2] = t1x; ne.tri[3] = t1y;
+                    ne.tri[4] = t2x; ne.tri[5] = t2y;
+                    ne.level = L + 1;
+                    ne.child = c;
+                    ne.mask = s_fail;
+                    s_sp = s_sp + 1;
+                }
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+    singular = wave_or(singular);
+    if (lane == 0) {
+        if (singular) a.flags[kFlagSingular] = 1;
+        atomicAdd(&a.stats[kStatNear], st_pairs);
+        atomicAdd(&a.stats[kStatVisits], st_visits);
+        atomicAdd(&a.stats[kStatChecks], st_checks);
+        atomicAdd(&a.stats[kStatNonconv], st_nonconv);
+        atomicMax(&a.stats[kStatMaxLevel], st_maxlev);
+    }
+}
+
+// ------------------------------------------------------ work items
+
+// Near pairs per patch.
+__global__ void k_patch_count(int64_t np, const int32_t *pair_patch, const int8_t *pair_self,
+                              int64_t *pcount)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np || pair_self[p]) return;
+    atomicAdd((unsigned long long *)&pcount[pair_patch[p]], 1ull);
+}
+
+__global__ void k_patch_chunks(int64_t P, const int64_t *pcount, int64_t *nchunk)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= P) return;
+    nchunk[j] = (pcount[j] + 63) / 64;
+}
+
+// Scatter near pairs into patch-major order.
+__global__ void k_patch_scatter(int64_t np, const int32_t *pair_patch, const int8_t *pair_self,
+                                const int64_t *pptr, unsigned long long *pcursor, int32_t *plist)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np || pair_self[p]) return;
+    const int j = pair_patch[p];
+    const unsigned long long k = atomicAdd(&pcursor[j], 1ull);
+    plist[pptr[j] + (int64_t)k] = (int32_t)p;
+}
+
+// Work items (patch, start, count <= 64) into per-degree segments.  Block-
+// aggregated: one global atomic per (block, degree).
+__global__ __launch_bounds__(256) void k_items(int64_t P, const int32_t *degree,
+                                               const int64_t *pcount, const int64_t *pptr,
+                                               const int64_t *item_seg_start,
+                                               unsigned long long *item_cursor, int32_t *items)
+{
+    __shared__ unsigned int s_cnt[9];
+    __shared__ unsigned long long s_base[9];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (threadIdx.x < 9) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int d = 0, nch = 0;
+    unsigned int local = 0;
+    if (j < P) {
+        d = degree[j];
+        nch = (int)((pcount[j] + 63) / 64);
+        if (nch > 0) local = atomicAdd(&s_cnt[d], (unsigned)nch);
+    }
+    __syncthreads();
+    if (threadIdx.x < 9 && s_cnt[threadIdx.x] > 0)
+        s_base[threadIdx.x] = atomicAdd(&item_cursor[threadIdx.x], (unsigned long long)s_cnt[threadIdx.x]);
+    __syncthreads();
+    if (j < P && nch > 0) {
+        const int64_t base = item_seg_start[d] + (int64_t)s_base[d] + local;
+        for (int c = 0; c < nch; ++c) {
+            int32_t *it = items + 3 * (base + c);
+            const int64_t st = pptr[j] + 64 * c;
+            const int64_t rem = pcount[j] - 64 * c;
+            it[0] = (int32_t)j;
+            it[1] = (int32_t)st;
+            it[2] = (int32_t)(rem < 64 ? rem : 64);
+        }
+    }
+}
+
+}  // namespace nfq

@@ -10,6 +10,7 @@
 
 #include "nfq.h"
 #include "kernels.hpp"
+#include "near_patch.hpp"
 #include "tables.hpp"
 
 using namespace nfq;
@@ -51,6 +52,18 @@ struct nfq_plan {
     int present_mask = 0;
     int max_degree = 0;
     int value_kind = -1;  // value type of the last generate: 0 double, 1 complex128
+    // patch-centric near work items
+    std::vector<int64_t *> scan_tmp_p;  // scan temporaries for P-sized arrays
+    int64_t n_near = 0;
+    int64_t *pcount = nullptr, *nchunk = nullptr, *pptr = nullptr, *cptr = nullptr;
+    unsigned long long *pcursor = nullptr;
+    int32_t *plist = nullptr;
+    int32_t *items = nullptr;
+    int64_t item_start_h[9] = {}, item_count_h[9] = {}, n_items = 0;
+    int64_t *item_start = nullptr;
+    unsigned long long *item_cursor = nullptr;
+    double *mom = nullptr;
+    int64_t mom_slots = 0, mom_slot = 0;
     hipEvent_t ev[2 * 5 * 9] = {};  // phase timing events (begin, end) x phase x degree
     bool ev_ok = false;
 };
@@ -112,7 +125,7 @@ int64_t pad16(int64_t n) { return (n + 15) / 16 * 16; }
 
 // Exclusive scan of a_in, b_in (length n) into a_out, b_out (length n + 1).
 nfq_status run_scan(nfq_plan *pl, int64_t n, const int64_t *a_in, const int64_t *b_in,
-                    int64_t *a_out, int64_t *b_out)
+                    int64_t *a_out, int64_t *b_out, std::vector<int64_t *> &tmp)
 {
     hipStream_t st = pl->ctx->stream;
     // level sizes
@@ -130,8 +143,8 @@ nfq_status run_scan(nfq_plan *pl, int64_t n, const int64_t *a_in, const int64_t 
     for (size_t lv = 0; lv < sizes.size(); ++lv) {
         const int64_t len = sizes[lv];
         const int64_t tiles = (len + kScanTile - 1) / kScanTile;
-        int64_t *ta = pl->scan_tmp[4 * lv + 0], *tb = pl->scan_tmp[4 * lv + 1];
-        int64_t *na = pl->scan_tmp[4 * lv + 2], *nb2 = pl->scan_tmp[4 * lv + 3];
+        int64_t *ta = tmp[4 * lv + 0], *tb = tmp[4 * lv + 1];
+        int64_t *na = tmp[4 * lv + 2], *nb2 = tmp[4 * lv + 3];
         if (len > 0)
             hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, len, ia,
                                ib, oa, ob, ta, tb);
@@ -151,6 +164,55 @@ nfq_status run_scan(nfq_plan *pl, int64_t n, const int64_t *a_in, const int64_t 
     hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(64), 0, st, n, a_in, b_in, a_out, b_out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(pl->ctx, NFQ_ERR_HIP, hipGetErrorString(e));
+    return NFQ_OK;
+}
+
+hipError_t alloc_scan_tmp(int64_t n, std::vector<int64_t *> &tmp)
+{
+    int64_t m = n;
+    while (true) {
+        const int64_t tiles = (m + kScanTile - 1) / kScanTile;
+        for (int k = 0; k < 4; ++k) {
+            int64_t *p = nullptr;
+            hipError_t e = dalloc(&p, tiles + 1);
+            if (e != hipSuccess) return e;
+            tmp.push_back(p);
+        }
+        if (m <= kScanTile) break;
+        m = tiles;
+    }
+    return hipSuccess;
+}
+
+// Per-degree count of work items (chunks of <= 64 near targets of a patch).
+__global__ void k_item_count(int64_t P, const int32_t *degree, const int64_t *nchunk,
+                             unsigned long long *cnt)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= P || nchunk[j] == 0) return;
+    atomicAdd(&cnt[degree[j]], (unsigned long long)nchunk[j]);
+}
+
+// Patch-major near pairs and work items (generate-time builder part).
+nfq_status build_items(nfq_plan *pl, hipStream_t st)
+{
+    nfq_ctx *ctx = pl->ctx;
+    const int64_t P = pl->pb.P, np = pl->npairs;
+    HIP_TRY(ctx, hipMemsetAsync(pl->pcount, 0, P * 8, st));
+    HIP_TRY(ctx, hipMemsetAsync(pl->pcursor, 0, P * 8, st));
+    HIP_TRY(ctx, hipMemsetAsync(pl->item_cursor, 0, 9 * 8, st));
+    if (np > 0)
+        hipLaunchKernelGGL(k_patch_count, dim3(nblk(np, 256)), dim3(256), 0, st, np, pl->pair_patch,
+                           pl->pair_self, pl->pcount);
+    hipLaunchKernelGGL(k_patch_chunks, dim3(nblk(P, 256)), dim3(256), 0, st, P, pl->pcount, pl->nchunk);
+    nfq_status s = run_scan(pl, P, pl->pcount, pl->nchunk, pl->pptr, pl->cptr, pl->scan_tmp_p);
+    if (s != NFQ_OK) return s;
+    if (np > 0)
+        hipLaunchKernelGGL(k_patch_scatter, dim3(nblk(np, 256)), dim3(256), 0, st, np, pl->pair_patch,
+                           pl->pair_self, pl->pptr, pl->pcursor, pl->plist);
+    hipLaunchKernelGGL(k_items, dim3(nblk(P, 256)), dim3(256), 0, st, P, pl->pb.degree, pl->pcount,
+                       pl->pptr, pl->item_start, pl->item_cursor, pl->items);
+    HIP_TRY(ctx, hipGetLastError());
     return NFQ_OK;
 }
 
@@ -180,24 +242,33 @@ nfq_status check_flags(nfq_ctx *ctx, const int *hflags)
 
 template <int D, bool CPLX>
 void launch_quad(const nfq_plan *pl, QuadArgs qa, int64_t near_seg, int64_t near_cnt,
-                 int64_t self_seg, int64_t self_cnt, hipStream_t st, Timer &tm)
+                 int64_t self_seg, int64_t self_cnt, hipStream_t st, Timer &tm, bool per_pair,
+                 PatchArgs pa)
 {
     using S = QuadShape<D, CPLX>;
     if (self_cnt > 0) {
         qa.seg = self_seg;
         qa.count = self_cnt;
-        const unsigned blocks = nblk(self_cnt, S::WPB);
+        using SS = SelfShape<D, CPLX>;
+        const unsigned blocks = nblk(self_cnt, SS::WPB);
         tm.begin(kPhSelf, D, st);
-        hipLaunchKernelGGL((k_self<D, CPLX>), dim3(blocks), dim3(64 * S::WPB), 0, st, qa);
+        hipLaunchKernelGGL((k_self<D, CPLX>), dim3(blocks), dim3(64 * SS::WPB), 0, st, qa);
         tm.end(kPhSelf, D, st);
     }
-    if (near_cnt > 0) {
+    if (near_cnt > 0 && per_pair) {
         qa.seg = near_seg;
         qa.count = near_cnt;
         const int64_t max_blocks = pl->stack_waves / S::WPB;
         const unsigned blocks = (unsigned)std::min<int64_t>(nblk(near_cnt, S::WPB), max_blocks);
         tm.begin(kPhNear, D, st);
         hipLaunchKernelGGL((k_near<D, CPLX>), dim3(blocks), dim3(64 * S::WPB), 0, st, qa);
+        tm.end(kPhNear, D, st);
+    } else if (pl->item_count_h[D] > 0) {
+        pa.item_seg = pl->item_start_h[D];
+        pa.item_count = pl->item_count_h[D];
+        const unsigned blocks = (unsigned)std::min<int64_t>(pa.item_count, pl->mom_slots);
+        tm.begin(kPhNear, D, st);
+        hipLaunchKernelGGL((k_near_patch<D, CPLX>), dim3(blocks), dim3(256), 0, st, pa);
         tm.end(kPhNear, D, st);
     }
     const int64_t tot = near_cnt + self_cnt;  // both padded to 16, contiguous
@@ -211,17 +282,17 @@ void launch_quad(const nfq_plan *pl, QuadArgs qa, int64_t near_seg, int64_t near
 
 template <bool CPLX>
 void launch_degree(int d, const nfq_plan *pl, const QuadArgs &qa, int64_t ns, int64_t nc,
-                   int64_t ss, int64_t sc, hipStream_t st, Timer &tm)
+                   int64_t ss, int64_t sc, hipStream_t st, Timer &tm, bool pp, const PatchArgs &pa)
 {
     switch (d) {
-    case 1: launch_quad<1, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
-    case 2: launch_quad<2, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
-    case 3: launch_quad<3, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
-    case 4: launch_quad<4, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
-    case 5: launch_quad<5, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
-    case 6: launch_quad<6, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
-    case 7: launch_quad<7, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
-    case 8: launch_quad<8, CPLX>(pl, qa, ns, nc, ss, sc, st, tm); break;
+    case 1: launch_quad<1, CPLX>(pl, qa, ns, nc, ss, sc, st, tm, pp, pa); break;
+    case 2: launch_quad<2, CPLX>(pl, qa, ns, nc, ss, sc, st, tm, pp, pa); break;
+    case 3: launch_quad<3, CPLX>(pl, qa, ns, nc, ss, sc, st, tm, pp, pa); break;
+    case 4: launch_quad<4, CPLX>(pl, qa, ns, nc, ss, sc, st, tm, pp, pa); break;
+    case 5: launch_quad<5, CPLX>(pl, qa, ns, nc, ss, sc, st, tm, pp, pa); break;
+    case 6: launch_quad<6, CPLX>(pl, qa, ns, nc, ss, sc, st, tm, pp, pa); break;
+    case 7: launch_quad<7, CPLX>(pl, qa, ns, nc, ss, sc, st, tm, pp, pa); break;
+    case 8: launch_quad<8, CPLX>(pl, qa, ns, nc, ss, sc, st, tm, pp, pa); break;
     default: break;
     }
 }
@@ -341,6 +412,12 @@ void nfq_plan_destroy(nfq_plan *pl)
         if (p) (void)hipFree(p);
     for (int64_t *p : pl->scan_tmp)
         if (p) (void)hipFree(p);
+    for (int64_t *p : pl->scan_tmp_p)
+        if (p) (void)hipFree(p);
+    void *ptrs2[] = {pl->pcount, pl->nchunk, pl->pptr, pl->cptr, pl->pcursor, pl->plist, pl->items,
+                     pl->item_start, pl->item_cursor, pl->mom};
+    for (void *p : ptrs2)
+        if (p) (void)hipFree(p);
     if (pl->ev_ok)
         for (auto &e : pl->ev) (void)hipEventDestroy(e);
     delete pl;
@@ -419,7 +496,7 @@ nfq_status nfq_plan_create(nfq_ctx *ctx, const nfq_surface *surf, const nfq_targ
     if (NT > 0)
         hipLaunchKernelGGL(k_rowlen, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, pl->present_mask,
                            pl->rowlen, pl->npair, pl->counts, pl->flags);
-    nfq_status s = run_scan(pl, NT, pl->rowlen, pl->npair, row_ptr, pl->pair_ptr);
+    nfq_status s = run_scan(pl, NT, pl->rowlen, pl->npair, row_ptr, pl->pair_ptr, pl->scan_tmp);
     if (s != NFQ_OK) return cleanup(s);
     int hflags[kNumFlags];
     PL_TRY(hipMemcpyAsync(hflags, pl->flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
@@ -452,6 +529,46 @@ nfq_status nfq_plan_create(nfq_ctx *ctx, const nfq_surface *surf, const nfq_targ
     PL_TRY(hipMemcpy(pl->seg_start, pl->seg_start_h, sizeof(pl->seg_start_h), hipMemcpyHostToDevice));
     PL_TRY(dalloc(&pl->coef, 3 * pb.N));
     PL_TRY(dalloc(&pl->tau, pb.P));
+    // patch-major work items of the near kernel: sized here, built in generate
+    {
+        const int64_t P = pb.P;
+        PL_TRY(dalloc(&pl->pcount, P));
+        PL_TRY(dalloc(&pl->nchunk, P));
+        PL_TRY(dalloc(&pl->pptr, P + 1));
+        PL_TRY(dalloc(&pl->cptr, P + 1));
+        PL_TRY(dalloc(&pl->pcursor, P));
+        PL_TRY(dalloc(&pl->item_start, 9));
+        PL_TRY(dalloc(&pl->item_cursor, 9));
+        PL_TRY(alloc_scan_tmp(P, pl->scan_tmp_p));
+        for (int d = 1; d <= 8; ++d) pl->n_near += pl->count_h[d];
+        PL_TRY(dalloc(&pl->plist, pl->n_near));
+        if (NT > 0)
+            hipLaunchKernelGGL(k_pairs, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, row_ptr,
+                               pl->pair_ptr, pl->pair_tgt, pl->pair_patch, pl->pair_self,
+                               pl->pair_off, (int32_t *)nullptr);
+        PL_TRY(hipMemsetAsync(pl->pcount, 0, P * 8, st));
+        PL_TRY(hipMemsetAsync(pl->item_cursor, 0, 9 * 8, st));
+        if (np > 0)
+            hipLaunchKernelGGL(k_patch_count, dim3(nblk(np, 256)), dim3(256), 0, st, np,
+                               pl->pair_patch, pl->pair_self, pl->pcount);
+        hipLaunchKernelGGL(k_patch_chunks, dim3(nblk(P, 256)), dim3(256), 0, st, P, pl->pcount,
+                           pl->nchunk);
+        hipLaunchKernelGGL(k_item_count, dim3(nblk(P, 256)), dim3(256), 0, st, P, pb.degree,
+                           pl->nchunk, pl->item_cursor);
+        unsigned long long hic[9];
+        PL_TRY(hipMemcpyAsync(hic, pl->item_cursor, sizeof(hic), hipMemcpyDeviceToHost, st));
+        PL_TRY(hipStreamSynchronize(st));
+        int64_t ipos = 0;
+        for (int d = 0; d < 9; ++d) {
+            pl->item_start_h[d] = ipos;
+            pl->item_count_h[d] = (int64_t)hic[d];
+            ipos += (int64_t)hic[d];
+        }
+        pl->n_items = ipos;
+        PL_TRY(dalloc(&pl->items, 3 * ipos));
+        PL_TRY(hipMemcpy(pl->item_start, pl->item_start_h, sizeof(pl->item_start_h),
+                         hipMemcpyHostToDevice));
+    }
     // DFS stacks for the persistent near kernel: enough wavefronts to fill the chip
     {
         int ncu = 0;
@@ -501,7 +618,7 @@ nfq_status nfq_generate(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *
     if (NT > 0)
         hipLaunchKernelGGL(k_rowlen, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, pl->present_mask,
                            pl->rowlen, pl->npair, (unsigned long long *)nullptr, pl->flags);
-    nfq_status s = run_scan(pl, NT, pl->rowlen, pl->npair, pl->row_ptr, pl->pair_ptr);
+    nfq_status s = run_scan(pl, NT, pl->rowlen, pl->npair, pl->row_ptr, pl->pair_ptr, pl->scan_tmp);
     if (s != NFQ_OK) return s;
     if (NT > 0)
         hipLaunchKernelGGL(k_pairs, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, pl->row_ptr,
@@ -511,6 +628,11 @@ nfq_status nfq_generate(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *
         hipLaunchKernelGGL(k_group, dim3(nblk(pl->npairs, 256)), dim3(256), 0, st, pl->npairs,
                            pl->pair_patch, pl->pair_self, pb.degree, pl->seg_start, pl->cursor,
                            pl->grp);
+    const bool per_pair = (prm->flags & NFQ_FLAG_PER_PAIR) != 0;
+    if (!per_pair) {
+        nfq_status sb = build_items(pl, st);
+        if (sb != NFQ_OK) return sb;
+    }
     tm.end(kPhBuilder, 0, st);
     // patch preparation
     DegTab tab = make_tab(ctx);
@@ -540,12 +662,44 @@ nfq_status nfq_generate(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *
     qa.stack = pl->stack;
     qa.flags = pl->flags;
     qa.stats = pl->stats;
+    PatchArgs pa{};
+    if (!per_pair) {
+        // per-slot moment storage of the patch kernel: [max_depth + 1][4][64][W]
+        const int64_t wmax = (2 * nd_of(pl->max_degree) + 15) / 16 * 16;
+        const int64_t need = (int64_t)(prm->max_depth + 1) * 4 * 64 * wmax;
+        if (need > pl->mom_slot || !pl->mom) {
+            if (pl->mom) (void)hipFree(pl->mom);
+            pl->mom = nullptr;
+            int ncu = 0;
+            HIP_TRY(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+            pl->mom_slots = (int64_t)std::max(ncu, 1) * 2;
+            HIP_TRY(ctx, dalloc(&pl->mom, pl->mom_slots * need));
+            pl->mom_slot = need;
+        }
+        pa.pb = pb;
+        pa.tab = tab;
+        pa.kern = qa.kern;
+        pa.helm = qa.helm;
+        pa.max_depth = prm->max_depth;
+        pa.rule = ctx->drule;
+        pa.items = pl->items;
+        pa.plist = pl->plist;
+        pa.pair_tgt = pl->pair_tgt;
+        pa.pair_off = pl->pair_off;
+        pa.coef = pl->coef;
+        pa.tau = pl->tau;
+        pa.val = (double *)val;
+        pa.mom = pl->mom;
+        pa.mom_slot = pl->mom_slot;
+        pa.flags = pl->flags;
+        pa.stats = pl->stats;
+    }
     for (int d = 1; d <= 8; ++d) {
         const int64_t ns = pl->seg_start_h[d], nc = pl->seg_len_h[d];
         const int64_t ss = pl->seg_start_h[9 + d], sc = pl->seg_len_h[9 + d];
         if (nc + sc == 0) continue;
-        if (cplx) launch_degree<true>(d, pl, qa, ns, nc, ss, sc, st, tm);
-        else launch_degree<false>(d, pl, qa, ns, nc, ss, sc, st, tm);
+        if (cplx) launch_degree<true>(d, pl, qa, ns, nc, ss, sc, st, tm, per_pair, pa);
+        else launch_degree<false>(d, pl, qa, ns, nc, ss, sc, st, tm, per_pair, pa);
     }
     HIP_TRY(ctx, hipGetLastError());
     if (stats) {

@@ -27,8 +27,8 @@ from paper_2006_02545_amd import surfaces as S  # noqa: E402
 
 
 def small_mixed():
-    """Mixed degrees 1..8 on a small ellipsoid + torus (ragged rows)."""
-    return S.mixed_problem(seed=11, tol=1e-8, k=3.0, ell_freq=2, tor_grid=(10, 5), dmin=1,
+    """Mixed degrees 2..8 on a small ellipsoid + torus (ragged rows)."""
+    return S.mixed_problem(seed=11, tol=1e-8, k=3.0, ell_freq=3, tor_grid=(16, 6), dmin=2,
                            dmax=8)
 
 
