@@ -119,7 +119,9 @@ typedef struct {
                        bit 1 (NFQ_FLAG_PER_PAIR): use the plain per-pair near
                        kernel (one wavefront per pair, no reuse of subtriangle
                        geometry across targets) instead of the patch-centric one */
-    int32_t pad;
+    int32_t min_depth; /* subdivide at least this deep (0: adaptive from the
+                          root); min_depth = max_depth gives uniform trees,
+                          whose weights are smooth in the geometry */
 } nfq_params;
 
 #define NFQ_FLAG_TIMING 1
@@ -177,6 +179,21 @@ nfq_status nfq_generate(nfq_plan *plan, const nfq_kernel *kern, const nfq_params
  * same value type as val (complex128 interleaved or double). */
 nfq_status nfq_apply(nfq_plan *plan, const int32_t *col, const void *val, const void *sigma,
                      void *y);
+
+/* Adjoint (gradient) of Phi = sum_t conj(lambda_t) (A sigma)_t for the
+ * quadrature nfq_generate computes with the same kernel and parameters: the
+ * adaptive decisions are recomputed, then the quadrature sum over the
+ * accepted subtriangles (and the self rules, with their split points and
+ * grading held fixed) is differentiated.  sigma: device complex128 [N]
+ * (nodal density), lambda: device complex128 [NT].  Outputs (device,
+ * complex128, interleaved): grad_xyz [N][3] = dPhi/dx_node (chart nodes, plus
+ * the target position for node targets; each node may be the target of at
+ * most one target), grad_k [1] = dPhi/dk at fixed alpha, beta, and dphi_dab
+ * [2] = (dPhi/dalpha, dPhi/dbeta) or NULL.  Deterministic.  Not part of the
+ * paper (a companion for shape optimisation and inverse problems). */
+nfq_status nfq_adjoint(nfq_plan *plan, const nfq_kernel *kern, const nfq_params *params,
+                       const void *sigma, const void *lambda, void *grad_xyz, void *grad_k,
+                       void *dphi_dab);
 
 /* Wait for all work enqueued on the context's stream; reports device-side
  * errors of earlier calls. */

@@ -1,0 +1,671 @@
+// adjoint.hpp -- gradient of Phi = sum_t conj(lambda_t) (A sigma)_t with
+// respect to the patch nodes, the wavenumber and the kernel weights alpha,
+// beta, for the quadrature the forward generator computes (frozen
+// subdivision: the adaptive decisions are recomputed with the forward's own
+// arithmetic, then the quadrature sum over the accepted subtriangles is
+// differentiated).
+//
+// With sigma^j(u,v) = sum_nm s_nm K_nm(u,v), s = V sigma_j (Section 4.2) the
+// functional is a sum over pairs and accepted rule nodes q of
+//     w_q conj(lambda_t) sigma^j(y_q) Kern(x_t, X(y_q), n(y_q)).
+// For a node with r = x - X, R = |r|, E = e^{ikR},
+//     Kern = alpha J G + beta (n.r) F,  G = E/(4 pi R),
+//     F = (1 - ikR) E / (4 pi R^3),  F' = E (k^2 R^2 + 3ikR - 3) / (4 pi R^4),
+//     dKern/dX = -alpha J G' r/R - beta [F n + (n.r) F' r/R],
+//     G' = E (ikR - 1) / (4 pi R^2),
+//     dKern/dn = alpha G n/J + beta F r,
+//     dKern/dk = alpha J iR G + beta (n.r) k E / (4 pi R),
+// and dKern/dx_t = -dKern/dX.  The chart X = sum_nm chi_nm K_nm (chi = V x)
+// gives, per node, dPhi/dchi_nm = gX K_nm + (X_v x gn) dK_nm/du
+// + (gn x X_u) dK_nm/dv (gX, gn the weighted kernel derivatives), and
+// dPhi/dx_l = sum_nm V_(nm),l dPhi/dchi_nm.
+#pragma once
+
+#include "near_patch.hpp"
+
+namespace nfq {
+
+// Per-node gradient terms.  Inputs: target x, chart X, Xu, Xv, weight wq
+// (rule weight times |T|/|T0|), rho = conj(lambda) sigma(y) (complex).
+// Outputs: gX, gn (complex 3-vectors, already times rho wq), gk, the single-
+// and double-layer integrands phiS = J G rho wq, phiD = (n.r) F rho wq.
+struct NodeGrad {
+    double gXr[3], gXi[3], gnr[3], gni[3];
+    double gkr, gki, sr, si, dr, di;
+};
+
+__device__ __forceinline__ void cmul(double ar, double ai, double br, double bi, double &cr,
+                                     double &ci)
+{
+    cr = ar * br - ai * bi;
+    ci = ar * bi + ai * br;
+}
+
+__device__ __forceinline__ void node_grad(const Kern &k, const double x[3], const double X[3],
+                                          const double n[3], double wq, double rhor, double rhoi,
+                                          NodeGrad &g)
+{
+    const double rx = x[0] - X[0], ry = x[1] - X[1], rz = x[2] - X[2];
+    const double R2 = rx * rx + ry * ry + rz * rz;
+    const double Rinv = rsqrt_nr(R2);
+    const double R = R2 * Rinv;
+    const double J = __builtin_sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    const double nr = n[0] * rx + n[1] * ry + n[2] * rz;
+    double s, c;
+    sincos_cw(k.kr * R, &s, &c);
+    if (k.ki != 0.0) {
+        const double damp = exp(-k.ki * R);
+        s *= damp;
+        c *= damp;
+    }
+    // E = c + i s;  k = kr + i ki;  kR = (kr R, ki R)
+    const double q = kInv4Pi * Rinv;                 // 1/(4 pi R)
+    const double Gr = c * q, Gi = s * q;             // G
+    // ikR = (-ki R, kr R)
+    const double ikRr = -k.ki * R, ikRi = k.kr * R;
+    // F = (1 - ikR) E q / R^2
+    double Fr, Fi;
+    cmul(1.0 - ikRr, -ikRi, Gr, Gi, Fr, Fi);
+    Fr *= Rinv * Rinv;
+    Fi *= Rinv * Rinv;
+    // G' = E (ikR - 1) q / R
+    double Gpr, Gpi;
+    cmul(ikRr - 1.0, ikRi, Gr, Gi, Gpr, Gpi);
+    Gpr *= Rinv;
+    Gpi *= Rinv;
+    // F' = E (k^2 R^2 + 3 ikR - 3) q / R^3 ; k^2 R^2 = (kR)^2
+    const double kRr = k.kr * R, kRi = k.ki * R;
+    const double k2r = kRr * kRr - kRi * kRi, k2i = 2.0 * kRr * kRi;
+    double Fpr, Fpi;
+    cmul(k2r + 3.0 * ikRr - 3.0, k2i + 3.0 * ikRi, Gr, Gi, Fpr, Fpi);
+    const double R3inv = Rinv * Rinv * Rinv;
+    Fpr *= R3inv;
+    Fpi *= R3inv;
+    // weights: W = rho wq
+    const double Wr = rhor * wq, Wi = rhoi * wq;
+    // alpha W, beta W
+    double aWr, aWi, bWr, bWi;
+    cmul(k.ar, k.ai, Wr, Wi, aWr, aWi);
+    cmul(k.br, k.bi, Wr, Wi, bWr, bWi);
+    // dKern/dX = -alpha J G' r/R - beta [F n + (n.r) F' r/R]
+    double t1r, t1i, t2r, t2i, t3r, t3i;
+    cmul(aWr, aWi, Gpr, Gpi, t1r, t1i);            // alpha W G'
+    t1r *= -J * Rinv;
+    t1i *= -J * Rinv;
+    cmul(bWr, bWi, Fr, Fi, t2r, t2i);              // beta W F
+    cmul(bWr, bWi, Fpr, Fpi, t3r, t3i);            // beta W F'
+    t3r *= -nr * Rinv;
+    t3i *= -nr * Rinv;
+    const double rv[3] = {rx, ry, rz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        g.gXr[a] = (t1r + t3r) * rv[a] - t2r * n[a];
+        g.gXi[a] = (t1i + t3i) * rv[a] - t2i * n[a];
+    }
+    // dKern/dn = alpha G n/J + beta F r
+    double u1r, u1i;
+    cmul(aWr, aWi, Gr, Gi, u1r, u1i);
+    const double Jinv = 1.0 / J;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        g.gnr[a] = u1r * n[a] * Jinv + t2r * rv[a];
+        g.gni[a] = u1i * n[a] * Jinv + t2i * rv[a];
+    }
+    // dKern/dk = alpha J iR G + beta (n.r) k E q
+    double v1r, v1i, v2r, v2i;
+    cmul(u1r, u1i, 0.0, R * J, v1r, v1i);          // alpha W G * iR J
+    double kEr, kEi;
+    cmul(k.kr, k.ki, Gr, Gi, kEr, kEi);            // k E q
+    cmul(bWr, bWi, kEr * nr, kEi * nr, v2r, v2i);
+    g.gkr = v1r + v2r;
+    g.gki = v1i + v2i;
+    // single and double layer integrands (for dPhi/dalpha, dPhi/dbeta)
+    cmul(Wr, Wi, Gr * J, Gi * J, g.sr, g.si);
+    cmul(Wr, Wi, Fr * nr, Fi * nr, g.dr, g.di);
+}
+
+// Chart with the basis derivatives: K, Ku, Kv, X, Xu, Xv at (u,v).
+template <int D>
+__device__ __forceinline__ void chart_eval_d(const double *__restrict__ coef, double u, double v,
+                                             double *K, double *Ku, double *Kv, double X[3],
+                                             double Xu[3], double Xv[3])
+{
+    constexpr int ND = nd_of(D);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) X[c] = Xu[c] = Xv[c] = 0.0;
+    koorn_visit<D>(u, v, [&](int a, double k, double ku, double kv) {
+        K[a] = k;
+        Ku[a] = ku;
+        Kv[a] = kv;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double cf = coef[c * ND + a];
+            X[c] = __builtin_fma(cf, k, X[c]);
+            Xu[c] = __builtin_fma(cf, ku, Xu[c]);
+            Xv[c] = __builtin_fma(cf, kv, Xv[c]);
+        }
+    });
+}
+
+// Accumulate one node's contribution: GC[(c * ND + a) * 2 + {re, im}] +=
+// gX_c K_a + (Xv x gn)_c Ku_a + (gn x Xu)_c Kv_a; and the per-target sums.
+template <int ND>
+__device__ __forceinline__ void accumulate_node(const NodeGrad &g, const double *K,
+                                                const double *Ku, const double *Kv,
+                                                const double Xu[3], const double Xv[3],
+                                                double *GC, double *T12)
+{
+    // b = Xv x gn, d = gn x Xu (complex)
+    double br[3], bi[3], dr[3], di[3];
+    br[0] = Xv[1] * g.gnr[2] - Xv[2] * g.gnr[1];
+    br[1] = Xv[2] * g.gnr[0] - Xv[0] * g.gnr[2];
+    br[2] = Xv[0] * g.gnr[1] - Xv[1] * g.gnr[0];
+    bi[0] = Xv[1] * g.gni[2] - Xv[2] * g.gni[1];
+    bi[1] = Xv[2] * g.gni[0] - Xv[0] * g.gni[2];
+    bi[2] = Xv[0] * g.gni[1] - Xv[1] * g.gni[0];
+    dr[0] = g.gnr[1] * Xu[2] - g.gnr[2] * Xu[1];
+    dr[1] = g.gnr[2] * Xu[0] - g.gnr[0] * Xu[2];
+    dr[2] = g.gnr[0] * Xu[1] - g.gnr[1] * Xu[0];
+    di[0] = g.gni[1] * Xu[2] - g.gni[2] * Xu[1];
+    di[1] = g.gni[2] * Xu[0] - g.gni[0] * Xu[2];
+    di[2] = g.gni[0] * Xu[1] - g.gni[1] * Xu[0];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+            double *p = GC + 2 * (c * ND + a);
+            p[0] += g.gXr[c] * K[a] + br[c] * Ku[a] + dr[c] * Kv[a];
+            p[1] += g.gXi[c] * K[a] + bi[c] * Ku[a] + di[c] * Kv[a];
+        }
+    // target gradient -gX, dPhi/dk, phiS, phiD
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T12[2 * c] -= g.gXr[c];
+        T12[2 * c + 1] -= g.gXi[c];
+    }
+    T12[6] += g.gkr;
+    T12[7] += g.gki;
+    T12[8] += g.sr;
+    T12[9] += g.si;
+    T12[10] += g.dr;
+    T12[11] += g.di;
+}
+
+struct AdjArgs {
+    PatchArgs pa;             // forward arguments (val unused)
+    QuadArgs qa;              // self-rule arguments
+    const double *scoef;      // sigma coefficients per patch: [2 * node_ptr[j] + 2 a + {re,im}]
+    const double *lam;        // lambda per target (complex)
+    const int64_t *cptr;      // first chunk index of each patch
+    const int64_t *pptr;      // first patch-major near pair of each patch
+    double *gc_item;          // [chunks][6 ND_pad]: chart-coefficient gradient per work item
+    double *t_pair;           // [pairs][12]: target gradient, dk, phiS, phiD per pair
+    double *gc_self;          // [N][6 ND_pad]: chart-coefficient gradient per self pair (by node)
+    int gc_pitch;             // 6 * ND_max
+};
+
+// sigma(y) = sum_a s_a K_a (complex)
+template <int ND>
+__device__ __forceinline__ void sigma_at(const double *sc, const double *K, double &sr, double &si)
+{
+    sr = 0.0;
+    si = 0.0;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+        sr = __builtin_fma(sc[2 * a], K[a], sr);
+        si = __builtin_fma(sc[2 * a + 1], K[a], si);
+    }
+}
+
+// 64-lane sum into every lane (two butterfly stages per value).
+__device__ __forceinline__ double wave_sum64(double v) { return wave_sum(v); }
+
+template <int D>
+__global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
+{
+    using S = PatchShape<D, true>;
+    constexpr int ND = S::ND, NV = S::NV, W = S::W, PL = S::PL, GS = S::GS;
+    constexpr int NG = 6 * ND;  // real components of the chart-coefficient gradient
+    const PatchArgs &a = aa.pa;
+    __shared__ double s_geo[256 * GS];
+    __shared__ GroupEntry s_stack[kGroupStack];
+    __shared__ double s_x[64][3];
+    __shared__ double s_lam[64][2];
+    __shared__ int32_t s_pair[64];
+    __shared__ double s_t[64][12];
+    __shared__ double s_gw[4][NG];
+    __shared__ unsigned long long s_fail;
+    __shared__ int s_sp;
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int grp16 = lane >> 4, l16 = lane & 15;
+    double *mom = a.mom + (int64_t)blockIdx.x * a.mom_slot;
+    auto mptr = [&](int L, int c, int s) { return mom + ((int64_t)(L * 4 + c) * 64 + s) * W; };
+    int singular = 0;
+
+    for (int64_t it = blockIdx.x; it < a.item_count; it += gridDim.x) {
+        const int32_t *item = a.items + 3 * (a.item_seg + it);
+        const int j = item[0], start = item[1], count = item[2];
+        const double *cf = a.coef + 3 * a.pb.node_ptr[j];
+        const double *sc = aa.scoef + 2 * a.pb.node_ptr[j];
+        const double tau = a.tau[j];
+        if (tid < count) {
+            const int p = a.plist[start + tid];
+            const int64_t t = a.pair_tgt[p];
+            s_x[tid][0] = a.pb.txyz[3 * t];
+            s_x[tid][1] = a.pb.txyz[3 * t + 1];
+            s_x[tid][2] = a.pb.txyz[3 * t + 2];
+            s_lam[tid][0] = aa.lam[2 * t];
+            s_lam[tid][1] = -aa.lam[2 * t + 1];  // conj(lambda)
+            s_pair[tid] = p;
+        }
+        for (int k = tid; k < 64 * 12; k += 256) (&s_t[0][0])[k] = 0.0;
+        for (int k = tid; k < 4 * NG; k += 256) (&s_gw[0][0])[k] = 0.0;
+        if (tid < 64)
+            node_geometry<D>(cf, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, a.rule[3 * tid], a.rule[3 * tid + 1],
+                             a.rule[3 * tid + 2], s_geo + tid * GS);
+        __syncthreads();
+        // root moments (as in the forward)
+        for (int s = wv; s < count; s += 4) {
+            const double x[3] = {s_x[s][0], s_x[s][1], s_x[s][2]};
+            double acc[W];
+#pragma unroll
+            for (int v = 0; v < W; ++v) acc[v] = 0.0;
+            const double *g = s_geo + lane * GS;
+            double fr, fi;
+            kern_node(a.kern, a.helm, x, g, fr, fi, singular);
+#pragma unroll
+            for (int m = 0; m < ND; ++m) {
+                acc[2 * m] = fr * g[7 + m];
+                acc[2 * m + 1] = fi * g[7 + m];
+            }
+            reduce_scatter16<W>(acc, lane);
+#pragma unroll
+            for (int i = 0; i < PL; ++i) {
+                acc[i] += __shfl_xor(acc[i], 16, 64);
+                acc[i] += __shfl_xor(acc[i], 32, 64);
+            }
+            if (grp16 == 0) {
+                double *dst = mptr(0, 0, s);
+#pragma unroll
+                for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = acc[i];
+            }
+        }
+        if (tid == 0) {
+            GroupEntry &e = s_stack[0];
+            e.tri[0] = 0.0; e.tri[1] = 0.0; e.tri[2] = 1.0; e.tri[3] = 0.0; e.tri[4] = 0.0; e.tri[5] = 1.0;
+            e.level = 0;
+            e.child = 0;
+            e.mask = count == 64 ? ~0ull : ((1ull << count) - 1ull);
+            s_sp = 1;
+        }
+        __syncthreads();
+        // per-wave chart-coefficient gradient, accumulated in registers over
+        // every accepted check this wave handles
+        double GC[NG];
+#pragma unroll
+        for (int v = 0; v < NG; ++v) GC[v] = 0.0;
+        while (true) {
+            if (s_sp == 0) break;
+            const GroupEntry e = s_stack[s_sp - 1];
+            __syncthreads();
+            if (tid == 0) {
+                s_sp = s_sp - 1;
+                s_fail = 0ull;
+            }
+            const double ax = e.tri[0], ay = e.tri[1], bx = e.tri[2], by = e.tri[3];
+            const double cx = e.tri[4], cy = e.tri[5];
+            const double abx = 0.5 * (ax + bx), aby = 0.5 * (ay + by);
+            const double bcx = 0.5 * (bx + cx), bcy = 0.5 * (by + cy);
+            const double cax = 0.5 * (cx + ax), cay = 0.5 * (cy + ay);
+            const double area = __builtin_ldexp(1.0, -2 * (e.level + 1));
+            {
+                const int c = tid >> 6, q = tid & 63;
+                double Ax, Ay, Bx, By, Cx, Cy;
+                if (c == 0) { Ax = ax; Ay = ay; Bx = abx; By = aby; Cx = cax; Cy = cay; }
+                else if (c == 1) { Ax = abx; Ay = aby; Bx = bx; By = by; Cx = bcx; Cy = bcy; }
+                else if (c == 2) { Ax = cax; Ay = cay; Bx = bcx; By = bcy; Cx = cx; Cy = cy; }
+                else { Ax = bcx; Ay = bcy; Bx = cax; By = cay; Cx = abx; Cy = aby; }
+                node_geometry<D>(cf, Ax, Ay, Bx, By, Cx, Cy, a.rule[3 * q], a.rule[3 * q + 1],
+                                 a.rule[3 * q + 2] * area, s_geo + tid * GS);
+            }
+            __syncthreads();
+            const double thr = tau * __builtin_ldexp(1.0, -2 * e.level);
+            const int L = e.level;
+            // this lane's child triangle, for the gradient pass
+            double Ax, Ay, Bx, By, Cx, Cy;
+            if (grp16 == 0) { Ax = ax; Ay = ay; Bx = abx; By = aby; Cx = cax; Cy = cay; }
+            else if (grp16 == 1) { Ax = abx; Ay = aby; Bx = bx; By = by; Cx = bcx; Cy = bcy; }
+            else if (grp16 == 2) { Ax = cax; Ay = cay; Bx = bcx; By = bcy; Cx = cx; Cy = cy; }
+            else { Ax = bcx; Ay = bcy; Bx = cax; By = cay; Cx = abx; Cy = aby; }
+            unsigned long long mk = e.mask;
+            int k = 0;
+            while (mk) {
+                const int s = __builtin_ctzll(mk);
+                mk &= mk - 1ull;
+                if ((k++ & 3) != wv) continue;
+                const double x[3] = {s_x[s][0], s_x[s][1], s_x[s][2]};
+                double IT[PL];
+                {
+                    const double *src = mptr(L, e.child, s);
+#pragma unroll
+                    for (int i = 0; i < PL; ++i) IT[i] = src[PL * l16 + i];
+                }
+                double acc[W];
+#pragma unroll
+                for (int v = 0; v < W; ++v) acc[v] = 0.0;
+#pragma unroll 1
+                for (int i = 0; i < 4; ++i) {
+                    const double *g = s_geo + (grp16 * 64 + l16 + 16 * i) * GS;
+                    double fr, fi;
+                    kern_node(a.kern, a.helm, x, g, fr, fi, singular);
+#pragma unroll
+                    for (int m = 0; m < ND; ++m) {
+                        acc[2 * m] = __builtin_fma(fr, g[7 + m], acc[2 * m]);
+                        acc[2 * m + 1] = __builtin_fma(fi, g[7 + m], acc[2 * m + 1]);
+                    }
+                }
+                reduce_scatter16<W>(acc, lane);
+                double e2 = 0.0;
+#pragma unroll
+                for (int i = 0; i < PL; ++i) {
+                    double v = acc[i] + __shfl_xor(acc[i], 16, 64);
+                    v += __shfl_xor(v, 32, 64);
+                    const double df = v - IT[i];
+                    e2 += grp16 == 0 ? df * df : 0.0;
+                }
+                const double err2 = wave_sum(e2);
+                bool accept = err2 <= thr * thr && L + 1 >= a.min_depth;
+                if (!accept && L + 1 >= a.max_depth) accept = true;
+                if (accept) {
+                    // gradient pass over the 256 children nodes, 4 per lane
+                    const double lr = s_lam[s][0], li = s_lam[s][1];
+                    double T12[12];
+#pragma unroll
+                    for (int v = 0; v < 12; ++v) T12[v] = 0.0;
+#pragma unroll 1
+                    for (int i = 0; i < 4; ++i) {
+                        const int q = l16 + 16 * i;
+                        const double ru = a.rule[3 * q], rv = a.rule[3 * q + 1];
+                        const double wq = a.rule[3 * q + 2] * area;
+                        const double u = Ax + ru * (Bx - Ax) + rv * (Cx - Ax);
+                        const double v = Ay + ru * (By - Ay) + rv * (Cy - Ay);
+                        double K[ND], Ku[ND], Kv[ND], X[3], Xu[3], Xv[3];
+                        chart_eval_d<D>(cf, u, v, K, Ku, Kv, X, Xu, Xv);
+                        const double n[3] = {Xu[1] * Xv[2] - Xu[2] * Xv[1], Xu[2] * Xv[0] - Xu[0] * Xv[2],
+                                             Xu[0] * Xv[1] - Xu[1] * Xv[0]};
+                        double sgr, sgi, rhr, rhi;
+                        sigma_at<ND>(sc, K, sgr, sgi);
+                        cmul(lr, li, sgr, sgi, rhr, rhi);
+                        NodeGrad gg;
+                        node_grad(a.kern, x, X, n, wq, rhr, rhi, gg);
+                        accumulate_node<ND>(gg, K, Ku, Kv, Xu, Xv, GC, T12);
+                    }
+#pragma unroll
+                    for (int v = 0; v < 12; ++v) {
+                        const double tv = wave_sum(T12[v]);
+                        if (lane == 0) s_t[s][v] += tv;
+                    }
+                } else {
+                    double *dst = mptr(L + 1, grp16, s);
+#pragma unroll
+                    for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = acc[i];
+                    if (lane == 0) atomicOr(&s_fail, 1ull << s);
+                }
+            }
+            __syncthreads();
+            if (tid == 0 && s_fail != 0ull) {
+                for (int c = 3; c >= 0; --c) {
+                    GroupEntry &ne = s_stack[s_sp];
+                    double t0x, t0y, t1x, t1y, t2x, t2y;
+                    if (c == 0) { t0x = ax; t0y = ay; t1x = abx; t1y = aby; t2x = cax; t2y = cay; }
+                    else if (c == 1) { t0x = abx; t0y = aby; t1x = bx; t1y = by; t2x = bcx; t2y = bcy; }
+                    else if (c == 2) { t0x = cax; t0y = cay; t1x = bcx; t1y = bcy; t2x = cx; t2y = cy; }
+                    else { t0x = bcx; t0y = bcy; t1x = cax; t1y = cay; t2x = abx; t2y = aby; }
+                    ne.tri[0] = t0x; ne.tri[1] = t0y; ne.tri[2] = t1x; ne.tri[3] = t1y;
+                    ne.tri[4] = t2x; ne.tri[5] = t2y;
+                    ne.level = L + 1;
+                    ne.child = c;
+                    ne.mask = s_fail;
+                    s_sp = s_sp + 1;
+                }
+            }
+            __syncthreads();
+        }
+        // per-wave coefficient gradient: lane sums in fixed order, then the
+        // four waves in order
+#pragma unroll
+        for (int v = 0; v < NG; ++v) {
+            const double tv = wave_sum(GC[v]);
+            if (lane == 0) s_gw[wv][v] = tv;
+        }
+        __syncthreads();
+        {
+            const int64_t chunk = aa.cptr[j] + (start - aa.pptr[j]) / 64;
+            double *dst = aa.gc_item + chunk * aa.gc_pitch;
+            for (int v = tid; v < NG; v += 256) dst[v] = s_gw[0][v] + s_gw[1][v] + s_gw[2][v] + s_gw[3][v];
+            for (int k2 = tid; k2 < count * 12; k2 += 256) {
+                const int s = k2 / 12, v = k2 - s * 12;
+                aa.t_pair[(int64_t)s_pair[s] * 12 + v] = s_t[s][v];
+            }
+        }
+        __syncthreads();
+    }
+    singular = wave_or(singular);
+    if (lane == 0 && singular) a.flags[kFlagSingular] = 1;
+}
+
+// Self pairs: the forward's target-split rule, differentiated with the rule
+// (split points, sinh grading) held fixed.
+template <int D>
+__global__ __launch_bounds__(64) void k_adjoint_self(AdjArgs aa)
+{
+    constexpr int ND = nd_of(D);
+    constexpr int NG = 6 * ND;
+    const QuadArgs &a = aa.qa;
+    const int lane = threadIdx.x & 63;
+    const int nr = a.nr, na = a.na;
+    int singular = 0;
+    for (int64_t idx = blockIdx.x; idx < a.count; idx += gridDim.x) {
+        const int p = __builtin_amdgcn_readfirstlane(a.grp[a.seg + idx]);
+        if (p < 0) continue;
+        const int t = __builtin_amdgcn_readfirstlane(a.pair_tgt[p]);
+        const int j = __builtin_amdgcn_readfirstlane(a.pair_patch[p]);
+        const int64_t nb = a.pb.node_ptr[j];
+        const int64_t node = a.pb.node_of_target[t];
+        const int l = (int)(node - nb);
+        const double *cf = a.coef + 3 * nb;
+        const double *sc = aa.scoef + 2 * nb;
+        const double lr = aa.lam[2 * t], li = -aa.lam[2 * t + 1];
+        const double tu = a.tab.uv[D][2 * l], tv = a.tab.uv[D][2 * l + 1];
+        double x[3], G00, G01, G11;
+        {
+            double K[ND], Xu[3], Xv[3];
+            chart_eval<D>(cf, tu, tv, K, x, Xu, Xv);
+            G00 = Xu[0] * Xu[0] + Xu[1] * Xu[1] + Xu[2] * Xu[2];
+            G01 = Xu[0] * Xv[0] + Xu[1] * Xv[1] + Xu[2] * Xv[2];
+            G11 = Xv[0] * Xv[0] + Xv[1] * Xv[1] + Xv[2] * Xv[2];
+        }
+        double pA[6][2], pE[6][2], pmu[6], phl[6], pdet[6], pxa[6], pxb[6];
+        int npan = 0;
+        const double Pv[3][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}};
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const double Ax = Pv[e][0], Ay = Pv[e][1];
+            const double Ex = Pv[(e + 1) % 3][0] - Ax, Ey = Pv[(e + 1) % 3][1] - Ay;
+            const double EGE = G00 * Ex * Ex + 2.0 * G01 * Ex * Ey + G11 * Ey * Ey;
+            const double L = __builtin_sqrt(EGE);
+            const double rx = tu - Ax, ry = tv - Ay;
+            const double mu = (G00 * rx * Ex + G01 * (rx * Ey + ry * Ex) + G11 * ry * Ey) / EGE;
+            const double fx = Ax + mu * Ex - tu, fy = Ay + mu * Ey - tv;
+            const double h = __builtin_sqrt(G00 * fx * fx + 2.0 * G01 * fx * fy + G11 * fy * fy);
+            const double det = __builtin_fabs((Ax - tu) * Ey - (Ay - tv) * Ex);
+            const double x0 = asinh(-mu * L / h), x1 = asinh((1.0 - mu) * L / h);
+            const bool split = mu > 0.0 && mu < 1.0;
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                if (half == 1 && !split) break;
+                pA[npan][0] = Ax; pA[npan][1] = Ay; pE[npan][0] = Ex; pE[npan][1] = Ey;
+                pmu[npan] = mu; phl[npan] = h / L; pdet[npan] = det;
+                pxa[npan] = split ? (half == 0 ? x0 : 0.0) : x0;
+                pxb[npan] = split ? (half == 0 ? 0.0 : x1) : x1;
+                ++npan;
+            }
+        }
+        double GC[NG], T12[12];
+#pragma unroll
+        for (int v = 0; v < NG; ++v) GC[v] = 0.0;
+#pragma unroll
+        for (int v = 0; v < 12; ++v) T12[v] = 0.0;
+        const int per_panel = na * nr;
+        const int total = npan * per_panel;
+        for (int q = lane; q < total; q += 64) {
+            const int pi = q / per_panel;
+            const int rem = q - pi * per_panel;
+            const int ia = rem / nr, ir = rem - ia * nr;
+            double Ax = 0, Ay = 0, Ex = 0, Ey = 0, mu = 0, hl = 0, det = 0, xa = 0, xb = 0;
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                if (k == pi) {
+                    Ax = pA[k][0]; Ay = pA[k][1]; Ex = pE[k][0]; Ey = pE[k][1]; mu = pmu[k];
+                    hl = phl[k]; det = pdet[k]; xa = pxa[k]; xb = pxb[k];
+                }
+            const double xi = xa + (xb - xa) * a.gla[2 * ia];
+            const double lam = mu + hl * sinh(xi);
+            const double dlam = hl * cosh(xi) * (xb - xa) * a.gla[2 * ia + 1];
+            const double s = a.glr[2 * ir], ws = a.glr[2 * ir + 1];
+            const double dx = Ax + lam * Ex - tu, dy = Ay + lam * Ey - tv;
+            double K[ND], Ku[ND], Kv[ND], X[3], Xu[3], Xv[3];
+            chart_eval_d<D>(cf, tu + s * dx, tv + s * dy, K, Ku, Kv, X, Xu, Xv);
+            const double n[3] = {Xu[1] * Xv[2] - Xu[2] * Xv[1], Xu[2] * Xv[0] - Xu[0] * Xv[2],
+                                 Xu[0] * Xv[1] - Xu[1] * Xv[0]};
+            double sgr, sgi, rhr, rhi;
+            sigma_at<ND>(sc, K, sgr, sgi);
+            cmul(lr, li, sgr, sgi, rhr, rhi);
+            NodeGrad gg;
+            node_grad(a.kern, x, X, n, s * det * ws * dlam, rhr, rhi, gg);
+            accumulate_node<ND>(gg, K, Ku, Kv, Xu, Xv, GC, T12);
+        }
+        double *dst = aa.gc_self + node * aa.gc_pitch;
+#pragma unroll
+        for (int v = 0; v < NG; ++v) {
+            const double tv2 = wave_sum(GC[v]);
+            if (lane == 0) dst[v] = tv2;
+        }
+#pragma unroll
+        for (int v = 0; v < 12; ++v) {
+            const double tv2 = wave_sum(T12[v]);
+            if (lane == 0) aa.t_pair[(int64_t)p * 12 + v] = tv2;
+        }
+    }
+    (void)singular;
+}
+
+// sigma coefficients per patch: s = V sigma_j (complex).
+__global__ void k_sigma_coef(Problem pb, DegTab tab, const double *sigma, double *scoef)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= pb.P) return;
+    const int d = pb.degree[j];
+    const int nd = nd_of(d);
+    const double *V = tab.V[d];
+    const int64_t nb = pb.node_ptr[j];
+    for (int a = 0; a < nd; ++a) {
+        double sr = 0.0, si = 0.0;
+        for (int l = 0; l < nd; ++l) {
+            sr = __builtin_fma(V[a * nd + l], sigma[2 * (nb + l)], sr);
+            si = __builtin_fma(V[a * nd + l], sigma[2 * (nb + l) + 1], si);
+        }
+        scoef[2 * (nb + a)] = sr;
+        scoef[2 * (nb + a) + 1] = si;
+    }
+}
+
+// Node gradients from the chart-coefficient gradients: per patch, sum the
+// work-item parts (chunk order) and the self parts (node order), then
+// grad_l,c = sum_a V_(a),l G_c,a.
+__global__ void k_adj_patch_final(Problem pb, DegTab tab, const int64_t *cptr,
+                                  const int64_t *nchunk, const double *gc_item,
+                                  const double *gc_self, const unsigned int *is_self_node,
+                                  int pitch, double *grad)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= pb.P) return;
+    const int d = pb.degree[j];
+    const int nd = nd_of(d);
+    const double *V = tab.V[d];
+    const int64_t nb = pb.node_ptr[j];
+    double G[6 * kNDMax];
+    for (int v = 0; v < 6 * nd; ++v) G[v] = 0.0;
+    for (int64_t c = 0; c < nchunk[j]; ++c) {
+        const double *src = gc_item + (cptr[j] + c) * pitch;
+        for (int v = 0; v < 6 * nd; ++v) G[v] += src[v];
+    }
+    for (int l = 0; l < nd; ++l) {
+        if (!is_self_node[nb + l]) continue;
+        const double *src = gc_self + (nb + l) * pitch;
+        for (int v = 0; v < 6 * nd; ++v) G[v] += src[v];
+    }
+    for (int l = 0; l < nd; ++l)
+        for (int c = 0; c < 3; ++c) {
+            double gr = 0.0, gi = 0.0;
+            for (int a = 0; a < nd; ++a) {
+                const double vv = V[a * nd + l];
+                gr = __builtin_fma(vv, G[2 * (c * nd + a)], gr);
+                gi = __builtin_fma(vv, G[2 * (c * nd + a) + 1], gi);
+            }
+            grad[2 * (3 * (nb + l) + c)] = gr;
+            grad[2 * (3 * (nb + l) + c) + 1] = gi;
+        }
+}
+
+// Target gradients: for node targets, add the row's pair parts in row order.
+__global__ void k_adj_target_final(Problem pb, const int64_t *pair_ptr, const double *t_pair,
+                                   double *grad)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= pb.NT) return;
+    const int64_t node = pb.node_of_target[t];
+    if (node < 0) return;
+    double g[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t p = pair_ptr[t]; p < pair_ptr[t + 1]; ++p)
+        for (int v = 0; v < 6; ++v) g[v] += t_pair[p * 12 + v];
+    for (int v = 0; v < 6; ++v) grad[6 * node + v] += g[v];
+}
+
+// dPhi/dk, dPhi/dalpha = Phi_S, dPhi/dbeta = Phi_D: fixed-order block sum
+// over the pairs.
+__global__ __launch_bounds__(256) void k_adj_scalars(int64_t np, const double *t_pair,
+                                                     double *grad_k, double *dphi)
+{
+    __shared__ double s[256][6];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t p = threadIdx.x; p < np; p += 256)
+        for (int v = 0; v < 6; ++v) acc[v] += t_pair[p * 12 + 6 + v];
+    for (int v = 0; v < 6; ++v) s[threadIdx.x][v] = acc[v];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int v = 0; v < 6; ++v) s[threadIdx.x][v] += s[threadIdx.x + w][v];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        grad_k[0] = s[0][0];
+        grad_k[1] = s[0][1];
+        if (dphi)
+            for (int v = 0; v < 4; ++v) dphi[v] = s[0][2 + v];
+    }
+}
+
+// Marks the nodes that are targets (their self parts exist); two targets on
+// one node are rejected (the target-gradient pass writes each node once).
+__global__ void k_mark_self_nodes(Problem pb, unsigned int *mark, int *flags)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= pb.NT) return;
+    const int64_t node = pb.node_of_target[t];
+    if (node < 0 || node >= pb.N) return;
+    if (atomicAdd(&mark[node], 1u) > 0u) flags[kFlagInvalid] = 1;
+}
+
+}  // namespace nfq

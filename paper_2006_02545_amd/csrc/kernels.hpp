@@ -306,6 +306,7 @@ struct QuadArgs {
     Kern kern;
     int helm;
     int max_depth;
+    int min_depth;
     const double *rule;   // [64][3] subtriangle rule (u, v, w)
     const double *glr;    // [nr][2] radial Gauss-Legendre (s, w) on [0,1]
     const double *gla;    // [na][2] angular Gauss-Legendre (t, w) on [0,1]
@@ -492,11 +493,12 @@ __global__ __launch_bounds__((64 * QuadShape<D, CPLX>::WPB)) void k_near(QuadArg
             const double thr = tau * __builtin_ldexp(1.0, -2 * depth);
             st_visits += 4;
             ++st_checks;
-            bool accept = err2 <= thr * thr;
+            const bool ok = err2 <= thr * thr;
+            bool accept = ok && depth + 1 >= a.min_depth;
             if (!accept && (depth + 1 >= a.max_depth || sp + 4 > kStack)) {
                 if (sp + 4 > kStack) overflow = 1;
                 accept = true;
-                nonconv = true;
+                if (!ok) nonconv = true;
             }
             if (accept) {
 #pragma unroll

@@ -34,6 +34,9 @@ struct PatchShape {
     static constexpr int W = (NV + 15) / 16 * 16;   // padded components
     static constexpr int PL = W / 16;                // components per lane after the reduce-scatter
     static constexpr int GS = (7 + ND) | 1;          // LDS doubles per node (odd pitch)
+    // per-target totals kept in LDS when they fit beside the geometry
+    static constexpr bool TOT_LDS = (64 * NV + 256 * GS) * 8 <= 140 * 1024;
+    static constexpr int TOTN = TOT_LDS ? 64 * NV : 1;
 };
 
 struct PatchArgs {
@@ -42,6 +45,7 @@ struct PatchArgs {
     Kern kern;
     int helm;
     int max_depth;
+    int min_depth;            // checks above this depth always refine
     const double *rule;       // [64][3]
     const int32_t *items;     // [n][3]: patch, start in plist, count (<= 64)
     int64_t item_seg, item_count;
@@ -144,6 +148,7 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
     constexpr int ND = S::ND, NV = S::NV, W = S::W, PL = S::PL, GS = S::GS;
     constexpr int C = CPLX ? 2 : 1;
     __shared__ double s_geo[256 * GS];
+    __shared__ double s_tot[S::TOTN];
     __shared__ GroupEntry s_stack[kGroupStack];
     __shared__ double s_x[64][3];
     __shared__ int64_t s_off[64];
@@ -171,8 +176,11 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
             s_x[tid][2] = a.pb.txyz[3 * t + 2];
             const int64_t off = a.pair_off[p];
             s_off[tid] = off;
-            for (int v = 0; v < NV; ++v) a.val[C * off + v] = 0.0;
+            if (!S::TOT_LDS)
+                for (int v = 0; v < NV; ++v) a.val[C * off + v] = 0.0;
         }
+        if (S::TOT_LDS)
+            for (int k = tid; k < 64 * NV; k += 256) s_tot[k] = 0.0;
         if (tid < 64) {
             // root geometry: node tid of the rule on T0
             node_geometry<D>(cf, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, a.rule[3 * tid], a.rule[3 * tid + 1],
@@ -253,6 +261,13 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                 mk &= mk - 1ull;
                 if ((k++ & 3) != wv) continue;
                 const double x[3] = {s_x[s][0], s_x[s][1], s_x[s][2]};
+                // parent moments: loads issued before the node work
+                double IT[PL];
+                {
+                    const double *src = mptr(L, e.child, s);
+#pragma unroll
+                    for (int i = 0; i < PL; ++i) IT[i] = src[PL * l16 + i];
+                }
                 double acc[W];
 #pragma unroll
                 for (int v = 0; v < W; ++v) acc[v] = 0.0;
@@ -275,29 +290,28 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                 reduce_scatter16<W>(acc, lane);
                 // acc[0..PL): components of child grp16's moments; the sum
                 // over the four children by two more exchanges
-                double Ssum[PL], IT[PL];
-                const double *src = mptr(L, e.child, s);
+                double Ssum[PL];
                 double e2 = 0.0;
 #pragma unroll
                 for (int i = 0; i < PL; ++i) {
                     double v = acc[i] + __shfl_xor(acc[i], 16, 64);
                     v += __shfl_xor(v, 32, 64);
                     Ssum[i] = v;
-                    IT[i] = src[PL * l16 + i];
                     const double df = v - IT[i];
                     e2 += grp16 == 0 ? df * df : 0.0;
                 }
                 const double err2 = wave_sum(e2);
                 ++st_checks;
                 st_visits += 4;
-                bool accept = err2 <= thr * thr;
+                const bool ok = err2 <= thr * thr;
+                bool accept = ok && L + 1 >= a.min_depth;
                 if (!accept && L + 1 >= a.max_depth) {
                     accept = true;
-                    ++st_nonconv;
+                    if (!ok) ++st_nonconv;
                 }
                 if (accept) {
                     if (grp16 == 0) {
-                        double *dst = a.val + C * s_off[s];
+                        double *dst = S::TOT_LDS ? s_tot + s * NV : a.val + C * s_off[s];
 #pragma unroll
                         for (int i = 0; i < PL; ++i) {
                             const int comp = PL * l16 + i;
@@ -332,6 +346,11 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
             }
             __syncthreads();
         }
+        if (S::TOT_LDS)
+            for (int k = tid; k < count * NV; k += 256) {
+                const int s = k / NV, v = k - s * NV;
+                a.val[C * s_off[s] + v] = s_tot[k];
+            }
         __syncthreads();
     }
     singular = wave_or(singular);

@@ -11,6 +11,7 @@
 #include "nfq.h"
 #include "kernels.hpp"
 #include "near_patch.hpp"
+#include "adjoint.hpp"
 #include "tables.hpp"
 
 using namespace nfq;
@@ -64,6 +65,10 @@ struct nfq_plan {
     unsigned long long *item_cursor = nullptr;
     double *mom = nullptr;
     int64_t mom_slots = 0, mom_slot = 0;
+    // adjoint scratch
+    double *scoef = nullptr, *gc_item = nullptr, *t_pair = nullptr, *gc_self = nullptr;
+    unsigned int *self_mark = nullptr;
+    int gc_pitch = 0;
     hipEvent_t ev[2 * 5 * 9] = {};  // phase timing events (begin, end) x phase x degree
     bool ev_ok = false;
 };
@@ -322,6 +327,102 @@ nfq_status ensure_self_rule(nfq_ctx *ctx, int nr, int na)
 
 }  // namespace
 
+// Builder, patch preparation and kernel arguments shared by generate and
+// adjoint.  col may be null (no column indices written).
+static nfq_status prepare(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *prm, int32_t *col,
+                   void *val, Timer &tm, bool per_pair, int nr, int na, QuadArgs &qa, PatchArgs &pa)
+{
+    nfq_ctx *ctx = pl->ctx;
+    hipStream_t st = ctx->stream;
+    const Problem &pb = pl->pb;
+    const int64_t NT = pb.NT;
+    HIP_TRY(ctx, hipMemsetAsync(pl->flags, 0, kNumFlags * sizeof(int), st));
+    HIP_TRY(ctx, hipMemsetAsync(pl->stats, 0, kNumStats * 8, st));
+    HIP_TRY(ctx, hipMemsetAsync(pl->cursor, 0, 18 * 8, st));
+    HIP_TRY(ctx, hipMemsetAsync(pl->grp, 0xff, pl->grp_len * sizeof(int32_t), st));
+    // pair / work-queue builder
+    tm.begin(kPhBuilder, 0, st);
+    if (NT > 0)
+        hipLaunchKernelGGL(k_rowlen, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, pl->present_mask,
+                           pl->rowlen, pl->npair, (unsigned long long *)nullptr, pl->flags);
+    nfq_status s = run_scan(pl, NT, pl->rowlen, pl->npair, pl->row_ptr, pl->pair_ptr, pl->scan_tmp);
+    if (s != NFQ_OK) return s;
+    if (NT > 0)
+        hipLaunchKernelGGL(k_pairs, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, pl->row_ptr,
+                           pl->pair_ptr, pl->pair_tgt, pl->pair_patch, pl->pair_self, pl->pair_off,
+                           col);
+    if (pl->npairs > 0)
+        hipLaunchKernelGGL(k_group, dim3(nblk(pl->npairs, 256)), dim3(256), 0, st, pl->npairs,
+                           pl->pair_patch, pl->pair_self, pb.degree, pl->seg_start, pl->cursor,
+                           pl->grp);
+    if (!per_pair) {
+        nfq_status sb = build_items(pl, st);
+        if (sb != NFQ_OK) return sb;
+    }
+    tm.end(kPhBuilder, 0, st);
+    // patch preparation
+    DegTab tab = make_tab(ctx);
+    tm.begin(kPhPrep, 0, st);
+    hipLaunchKernelGGL(k_prep, dim3(nblk(pb.P, 64)), dim3(64), 0, st, pb, tab,
+                       prm->loosen * prm->tol, pl->coef, pl->tau, pl->flags);
+    tm.end(kPhPrep, 0, st);
+    // quadratures and weights, per degree
+    qa.pb = pb;
+    qa.tab = tab;
+    qa.kern = Kern{kern->alpha_re, kern->alpha_im, kern->beta_re, kern->beta_im, kern->k_re, kern->k_im};
+    qa.helm = (kern->k_re != 0.0 || kern->k_im != 0.0) ? 1 : 0;
+    qa.max_depth = prm->max_depth;
+    qa.min_depth = prm->min_depth;
+    qa.rule = ctx->drule;
+    qa.glr = ctx->dglr;
+    qa.gla = ctx->dgla;
+    qa.nr = nr;
+    qa.na = na;
+    qa.grp = pl->grp;
+    qa.pair_tgt = pl->pair_tgt;
+    qa.pair_patch = pl->pair_patch;
+    qa.pair_off = pl->pair_off;
+    qa.coef = pl->coef;
+    qa.tau = pl->tau;
+    qa.val = (double *)val;
+    qa.stack = pl->stack;
+    qa.flags = pl->flags;
+    qa.stats = pl->stats;
+    if (!per_pair) {
+        // per-slot moment storage of the patch kernel: [max_depth + 1][4][64][W]
+        const int64_t wmax = (2 * nd_of(pl->max_degree) + 15) / 16 * 16;
+        const int64_t need = (int64_t)(prm->max_depth + 1) * 4 * 64 * wmax;
+        if (need > pl->mom_slot || !pl->mom) {
+            if (pl->mom) (void)hipFree(pl->mom);
+            pl->mom = nullptr;
+            int ncu = 0;
+            HIP_TRY(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+            pl->mom_slots = (int64_t)std::max(ncu, 1) * 2;
+            HIP_TRY(ctx, dalloc(&pl->mom, pl->mom_slots * need));
+            pl->mom_slot = need;
+        }
+        pa.pb = pb;
+        pa.tab = tab;
+        pa.kern = qa.kern;
+        pa.helm = qa.helm;
+        pa.max_depth = prm->max_depth;
+        pa.min_depth = prm->min_depth;
+        pa.rule = ctx->drule;
+        pa.items = pl->items;
+        pa.plist = pl->plist;
+        pa.pair_tgt = pl->pair_tgt;
+        pa.pair_off = pl->pair_off;
+        pa.coef = pl->coef;
+        pa.tau = pl->tau;
+        pa.val = (double *)val;
+        pa.mom = pl->mom;
+        pa.mom_slot = pl->mom_slot;
+        pa.flags = pl->flags;
+        pa.stats = pl->stats;
+    }
+    return NFQ_OK;
+}
+
 extern "C" {
 
 const char *nfq_status_str(nfq_status s)
@@ -415,7 +516,8 @@ void nfq_plan_destroy(nfq_plan *pl)
     for (int64_t *p : pl->scan_tmp_p)
         if (p) (void)hipFree(p);
     void *ptrs2[] = {pl->pcount, pl->nchunk, pl->pptr, pl->cptr, pl->pcursor, pl->plist, pl->items,
-                     pl->item_start, pl->item_cursor, pl->mom};
+                     pl->item_start, pl->item_cursor, pl->mom, pl->scoef, pl->gc_item, pl->t_pair,
+                     pl->gc_self, pl->self_mark};
     for (void *p : ptrs2)
         if (p) (void)hipFree(p);
     if (pl->ev_ok)
@@ -588,8 +690,9 @@ nfq_status nfq_generate(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *
 {
     if (!pl || !kern || !prm || !col || !val) return fail(pl ? pl->ctx : nullptr, NFQ_ERR_INVALID_ARG, "null argument");
     nfq_ctx *ctx = pl->ctx;
-    if (!(prm->tol > 0.0) || !(prm->loosen > 0.0) || prm->max_depth < 1 || prm->max_depth > kMaxDepth)
-        return fail(ctx, NFQ_ERR_INVALID_ARG, "tol, loosen must be > 0; max_depth in 1..32");
+    if (!(prm->tol > 0.0) || !(prm->loosen > 0.0) || prm->max_depth < 1 || prm->max_depth > kMaxDepth ||
+        prm->min_depth < 0 || prm->min_depth > prm->max_depth)
+        return fail(ctx, NFQ_ERR_INVALID_ARG, "tol, loosen must be > 0; 0 <= min_depth <= max_depth <= 32");
     if (prm->ng != 0 && prm->ng != kNG) return fail(ctx, NFQ_ERR_UNSUPPORTED, "only ng = 8 is supported");
     const int nr = prm->self_nr > 0 ? prm->self_nr : 10;
     const int na = prm->self_na > 0 ? prm->self_na : 16;
@@ -609,91 +712,11 @@ nfq_status nfq_generate(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *
         for (auto &e : pl->ev) HIP_TRY(ctx, hipEventCreate(&e));
         pl->ev_ok = true;
     }
-    HIP_TRY(ctx, hipMemsetAsync(pl->flags, 0, kNumFlags * sizeof(int), st));
-    HIP_TRY(ctx, hipMemsetAsync(pl->stats, 0, kNumStats * 8, st));
-    HIP_TRY(ctx, hipMemsetAsync(pl->cursor, 0, 18 * 8, st));
-    HIP_TRY(ctx, hipMemsetAsync(pl->grp, 0xff, pl->grp_len * sizeof(int32_t), st));
-    // pair / work-queue builder
-    tm.begin(kPhBuilder, 0, st);
-    if (NT > 0)
-        hipLaunchKernelGGL(k_rowlen, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, pl->present_mask,
-                           pl->rowlen, pl->npair, (unsigned long long *)nullptr, pl->flags);
-    nfq_status s = run_scan(pl, NT, pl->rowlen, pl->npair, pl->row_ptr, pl->pair_ptr, pl->scan_tmp);
-    if (s != NFQ_OK) return s;
-    if (NT > 0)
-        hipLaunchKernelGGL(k_pairs, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, pl->row_ptr,
-                           pl->pair_ptr, pl->pair_tgt, pl->pair_patch, pl->pair_self, pl->pair_off,
-                           col);
-    if (pl->npairs > 0)
-        hipLaunchKernelGGL(k_group, dim3(nblk(pl->npairs, 256)), dim3(256), 0, st, pl->npairs,
-                           pl->pair_patch, pl->pair_self, pb.degree, pl->seg_start, pl->cursor,
-                           pl->grp);
     const bool per_pair = (prm->flags & NFQ_FLAG_PER_PAIR) != 0;
-    if (!per_pair) {
-        nfq_status sb = build_items(pl, st);
-        if (sb != NFQ_OK) return sb;
-    }
-    tm.end(kPhBuilder, 0, st);
-    // patch preparation
-    DegTab tab = make_tab(ctx);
-    tm.begin(kPhPrep, 0, st);
-    hipLaunchKernelGGL(k_prep, dim3(nblk(pb.P, 64)), dim3(64), 0, st, pb, tab,
-                       prm->loosen * prm->tol, pl->coef, pl->tau, pl->flags);
-    tm.end(kPhPrep, 0, st);
-    // quadratures and weights, per degree
     QuadArgs qa{};
-    qa.pb = pb;
-    qa.tab = tab;
-    qa.kern = Kern{kern->alpha_re, kern->alpha_im, kern->beta_re, kern->beta_im, kern->k_re, kern->k_im};
-    qa.helm = (kern->k_re != 0.0 || kern->k_im != 0.0) ? 1 : 0;
-    qa.max_depth = prm->max_depth;
-    qa.rule = ctx->drule;
-    qa.glr = ctx->dglr;
-    qa.gla = ctx->dgla;
-    qa.nr = nr;
-    qa.na = na;
-    qa.grp = pl->grp;
-    qa.pair_tgt = pl->pair_tgt;
-    qa.pair_patch = pl->pair_patch;
-    qa.pair_off = pl->pair_off;
-    qa.coef = pl->coef;
-    qa.tau = pl->tau;
-    qa.val = (double *)val;
-    qa.stack = pl->stack;
-    qa.flags = pl->flags;
-    qa.stats = pl->stats;
     PatchArgs pa{};
-    if (!per_pair) {
-        // per-slot moment storage of the patch kernel: [max_depth + 1][4][64][W]
-        const int64_t wmax = (2 * nd_of(pl->max_degree) + 15) / 16 * 16;
-        const int64_t need = (int64_t)(prm->max_depth + 1) * 4 * 64 * wmax;
-        if (need > pl->mom_slot || !pl->mom) {
-            if (pl->mom) (void)hipFree(pl->mom);
-            pl->mom = nullptr;
-            int ncu = 0;
-            HIP_TRY(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
-            pl->mom_slots = (int64_t)std::max(ncu, 1) * 2;
-            HIP_TRY(ctx, dalloc(&pl->mom, pl->mom_slots * need));
-            pl->mom_slot = need;
-        }
-        pa.pb = pb;
-        pa.tab = tab;
-        pa.kern = qa.kern;
-        pa.helm = qa.helm;
-        pa.max_depth = prm->max_depth;
-        pa.rule = ctx->drule;
-        pa.items = pl->items;
-        pa.plist = pl->plist;
-        pa.pair_tgt = pl->pair_tgt;
-        pa.pair_off = pl->pair_off;
-        pa.coef = pl->coef;
-        pa.tau = pl->tau;
-        pa.val = (double *)val;
-        pa.mom = pl->mom;
-        pa.mom_slot = pl->mom_slot;
-        pa.flags = pl->flags;
-        pa.stats = pl->stats;
-    }
+    nfq_status sp = prepare(pl, kern, prm, col, val, tm, per_pair, nr, na, qa, pa);
+    if (sp != NFQ_OK) return sp;
     for (int d = 1; d <= 8; ++d) {
         const int64_t ns = pl->seg_start_h[d], nc = pl->seg_len_h[d];
         const int64_t ss = pl->seg_start_h[9 + d], sc = pl->seg_len_h[9 + d];
@@ -742,6 +765,110 @@ nfq_status nfq_apply(nfq_plan *pl, const int32_t *col, const void *val, const vo
                            col, (const double *)val, (const double *)sigma, (double *)y);
     HIP_TRY(ctx, hipGetLastError());
     return NFQ_OK;
+}
+
+
+nfq_status nfq_adjoint(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *prm,
+                       const void *sigma, const void *lambda, void *grad_xyz, void *grad_k,
+                       void *dphi_dab)
+{
+    if (!pl || !kern || !prm || !sigma || !lambda || !grad_xyz || !grad_k)
+        return fail(pl ? pl->ctx : nullptr, NFQ_ERR_INVALID_ARG, "null argument");
+    nfq_ctx *ctx = pl->ctx;
+    if (!(prm->tol > 0.0) || !(prm->loosen > 0.0) || prm->max_depth < 1 || prm->max_depth > kMaxDepth ||
+        prm->min_depth < 0 || prm->min_depth > prm->max_depth)
+        return fail(ctx, NFQ_ERR_INVALID_ARG, "tol, loosen must be > 0; 0 <= min_depth <= max_depth <= 32");
+    if (prm->ng != 0 && prm->ng != kNG) return fail(ctx, NFQ_ERR_UNSUPPORTED, "only ng = 8 is supported");
+    const int nr = prm->self_nr > 0 ? prm->self_nr : 10;
+    const int na = prm->self_na > 0 ? prm->self_na : 16;
+    if (nr > 64 || na > 64) return fail(ctx, NFQ_ERR_INVALID_ARG, "self rule sizes must be <= 64");
+    if (kern->k_im < 0.0) return fail(ctx, NFQ_ERR_INVALID_ARG, "Im k must be >= 0");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    nfq_status s0 = ensure_self_rule(ctx, nr, na);
+    if (s0 != NFQ_OK) return s0;
+    hipStream_t st = ctx->stream;
+    const Problem &pb = pl->pb;
+    const int64_t N = pb.N, NT = pb.NT;
+    // adjoint scratch (allocated on first use)
+    const int pitch = 6 * nd_of(pl->max_degree > 0 ? pl->max_degree : 1);
+    if (!pl->scoef || pl->gc_pitch < pitch) {
+        (void)hipFree(pl->scoef); (void)hipFree(pl->gc_item); (void)hipFree(pl->t_pair);
+        (void)hipFree(pl->gc_self); (void)hipFree(pl->self_mark);
+        pl->scoef = pl->gc_item = pl->t_pair = pl->gc_self = nullptr;
+        pl->self_mark = nullptr;
+        HIP_TRY(ctx, dalloc(&pl->scoef, 2 * N));
+        HIP_TRY(ctx, dalloc(&pl->gc_item, std::max<int64_t>(pl->n_items, 1) * pitch));
+        HIP_TRY(ctx, dalloc(&pl->t_pair, std::max<int64_t>(pl->npairs, 1) * 12));
+        HIP_TRY(ctx, dalloc(&pl->gc_self, N * pitch));
+        HIP_TRY(ctx, dalloc(&pl->self_mark, N));
+        pl->gc_pitch = pitch;
+    }
+    Timer tm{pl, false};
+    QuadArgs qa{};
+    PatchArgs pa{};
+    nfq_status sp = prepare(pl, kern, prm, nullptr, nullptr, tm, false, nr, na, qa, pa);
+    if (sp != NFQ_OK) return sp;
+    DegTab tab = make_tab(ctx);
+    HIP_TRY(ctx, hipMemsetAsync(pl->self_mark, 0, N * sizeof(unsigned int), st));
+    HIP_TRY(ctx, hipMemsetAsync(pl->t_pair, 0, std::max<int64_t>(pl->npairs, 1) * 12 * 8, st));
+    if (NT > 0)
+        hipLaunchKernelGGL(k_mark_self_nodes, dim3(nblk(NT, 256)), dim3(256), 0, st, pb,
+                           pl->self_mark, pl->flags);
+    hipLaunchKernelGGL(k_sigma_coef, dim3(nblk(pb.P, 64)), dim3(64), 0, st, pb, tab,
+                       (const double *)sigma, pl->scoef);
+    AdjArgs aa{};
+    aa.pa = pa;
+    aa.qa = qa;
+    aa.scoef = pl->scoef;
+    aa.lam = (const double *)lambda;
+    aa.cptr = pl->cptr;
+    aa.pptr = pl->pptr;
+    aa.gc_item = pl->gc_item;
+    aa.t_pair = pl->t_pair;
+    aa.gc_self = pl->gc_self;
+    aa.gc_pitch = pitch;
+    for (int d = 1; d <= 8; ++d) {
+        const int64_t ss = pl->seg_start_h[9 + d], sc = pl->seg_len_h[9 + d];
+        AdjArgs ad = aa;
+        if (sc > 0) {
+            ad.qa.seg = ss;
+            ad.qa.count = sc;
+            const unsigned blocks = (unsigned)std::min<int64_t>(sc, 4096);
+#define NFQ_ADJ_SELF(DD) hipLaunchKernelGGL(k_adjoint_self<DD>, dim3(blocks), dim3(64), 0, st, ad)
+            switch (d) {
+            case 1: NFQ_ADJ_SELF(1); break; case 2: NFQ_ADJ_SELF(2); break;
+            case 3: NFQ_ADJ_SELF(3); break; case 4: NFQ_ADJ_SELF(4); break;
+            case 5: NFQ_ADJ_SELF(5); break; case 6: NFQ_ADJ_SELF(6); break;
+            case 7: NFQ_ADJ_SELF(7); break; case 8: NFQ_ADJ_SELF(8); break;
+            }
+#undef NFQ_ADJ_SELF
+        }
+        if (pl->item_count_h[d] > 0) {
+            ad.pa.item_seg = pl->item_start_h[d];
+            ad.pa.item_count = pl->item_count_h[d];
+            const unsigned blocks = (unsigned)std::min<int64_t>(ad.pa.item_count, pl->mom_slots);
+#define NFQ_ADJ_NEAR(DD) hipLaunchKernelGGL(k_adjoint_patch<DD>, dim3(blocks), dim3(256), 0, st, ad)
+            switch (d) {
+            case 1: NFQ_ADJ_NEAR(1); break; case 2: NFQ_ADJ_NEAR(2); break;
+            case 3: NFQ_ADJ_NEAR(3); break; case 4: NFQ_ADJ_NEAR(4); break;
+            case 5: NFQ_ADJ_NEAR(5); break; case 6: NFQ_ADJ_NEAR(6); break;
+            case 7: NFQ_ADJ_NEAR(7); break; case 8: NFQ_ADJ_NEAR(8); break;
+            }
+#undef NFQ_ADJ_NEAR
+        }
+    }
+    hipLaunchKernelGGL(k_adj_patch_final, dim3(nblk(pb.P, 64)), dim3(64), 0, st, pb, tab, pl->cptr,
+                       pl->nchunk, pl->gc_item, pl->gc_self, pl->self_mark, pitch, (double *)grad_xyz);
+    if (NT > 0)
+        hipLaunchKernelGGL(k_adj_target_final, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, pl->pair_ptr,
+                           pl->t_pair, (double *)grad_xyz);
+    hipLaunchKernelGGL(k_adj_scalars, dim3(1), dim3(256), 0, st, pl->npairs, pl->t_pair,
+                       (double *)grad_k, (double *)dphi_dab);
+    HIP_TRY(ctx, hipGetLastError());
+    int hflags[kNumFlags];
+    HIP_TRY(ctx, hipMemcpyAsync(hflags, pl->flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    return check_flags(ctx, hflags);
 }
 
 nfq_status nfq_sync(nfq_ctx *ctx)

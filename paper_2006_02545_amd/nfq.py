@@ -22,8 +22,8 @@ STATUS = {0: "NFQ_OK", 1: "NFQ_WARN_NONCONVERGED", -1: "NFQ_ERR_INVALID_ARG",
           -7: "NFQ_ERR_UNSUPPORTED"}
 
 EXPORTED = ["nfq_create", "nfq_destroy", "nfq_register_degree", "nfq_plan_create",
-            "nfq_generate", "nfq_apply", "nfq_sync", "nfq_plan_destroy", "nfq_status_str",
-            "nfq_last_error"]
+            "nfq_generate", "nfq_apply", "nfq_adjoint", "nfq_sync", "nfq_plan_destroy",
+            "nfq_status_str", "nfq_last_error"]
 
 
 class Surface(C.Structure):
@@ -47,7 +47,7 @@ class Kernel(C.Structure):
 class Params(C.Structure):
     _fields_ = [("tol", C.c_double), ("loosen", C.c_double), ("max_depth", C.c_int32),
                 ("ng", C.c_int32), ("self_nr", C.c_int32), ("self_na", C.c_int32),
-                ("flags", C.c_int32), ("pad", C.c_int32)]
+                ("flags", C.c_int32), ("min_depth", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -62,6 +62,7 @@ class Stats(C.Structure):
 
 
 NFQ_FLAG_TIMING = 1
+NFQ_FLAG_PER_PAIR = 2
 
 
 class NfqError(RuntimeError):
@@ -95,6 +96,8 @@ def load(path: str = LIB_PATH):
     L.nfq_generate.argtypes = [vp, C.POINTER(Kernel), C.POINTER(Params), vp, vp, vp]
     L.nfq_generate.restype = i32
     L.nfq_apply.argtypes = [vp, vp, vp, vp, vp]
+    L.nfq_adjoint.argtypes = [vp, C.POINTER(Kernel), C.POINTER(Params), vp, vp, vp, vp, vp]
+    L.nfq_adjoint.restype = i32
     L.nfq_apply.restype = i32
     L.nfq_sync.argtypes = [vp]
     L.nfq_sync.restype = i32
@@ -195,7 +198,7 @@ class Plan:
         self.nnz = int(nnz.value)
 
     def generate(self, alpha, beta, k, tol, loosen=1.0, max_depth=16, self_nr=0, self_na=0,
-                 col=None, val=None, stats=True, timing=False):
+                 col=None, val=None, stats=True, timing=False, per_pair=False, min_depth=0):
         """Run the generator; returns (col, val, stats dict or None).  val is
         complex128 (or float64 for a real kernel) of length nnz."""
         torch = self.ctx.torch
@@ -208,14 +211,36 @@ class Plan:
             val = torch.empty(self.nnz, dtype=torch.float64 if real else torch.complex128,
                               device=dev)
         kern = Kernel(alpha.real, alpha.imag, beta.real, beta.imag, k.real, k.imag)
+        flags = (NFQ_FLAG_TIMING if timing else 0) | (NFQ_FLAG_PER_PAIR if per_pair else 0)
         prm = Params(float(tol), float(loosen), int(max_depth), 0, int(self_nr), int(self_na),
-                     NFQ_FLAG_TIMING if timing else 0, 0)
+                     flags, int(min_depth))
         st = Stats()
         rc = self.ctx.L.nfq_generate(self.h, C.byref(kern), C.byref(prm), _ptr(col), _ptr(val),
                                      C.byref(st) if stats else None)
         self.ctx._check(rc, self.ctx.h)
         self.last_status = rc
         return col, val, (st.as_dict() if stats else None)
+
+    def adjoint(self, alpha, beta, k, tol, sigma, lam, loosen=1.0, max_depth=16, self_nr=0,
+                self_na=0, min_depth=0):
+        """Gradient of Phi = sum_t conj(lam_t) (A sigma)_t: returns
+        (grad_xyz [N,3] complex, dPhi/dk, dPhi/dalpha, dPhi/dbeta)."""
+        torch = self.ctx.torch
+        dev = self.row_ptr.device
+        alpha, beta, k = complex(alpha), complex(beta), complex(k)
+        sig = torch.as_tensor(np.ascontiguousarray(sigma, dtype=np.complex128), device=dev)
+        lmb = torch.as_tensor(np.ascontiguousarray(lam, dtype=np.complex128), device=dev)
+        grad = torch.empty((self.N, 3), dtype=torch.complex128, device=dev)
+        gk = torch.empty(1, dtype=torch.complex128, device=dev)
+        dab = torch.empty(2, dtype=torch.complex128, device=dev)
+        kern = Kernel(alpha.real, alpha.imag, beta.real, beta.imag, k.real, k.imag)
+        prm = Params(float(tol), float(loosen), int(max_depth), 0, int(self_nr), int(self_na), 0,
+                     int(min_depth))
+        self.ctx._check(self.ctx.L.nfq_adjoint(self.h, C.byref(kern), C.byref(prm), _ptr(sig),
+                                               _ptr(lmb), _ptr(grad), _ptr(gk), _ptr(dab)),
+                        self.ctx.h)
+        self.ctx.torch.cuda.synchronize()
+        return grad.cpu().numpy(), complex(gk.cpu().numpy()[0]), *[complex(v) for v in dab.cpu().numpy()]
 
     def apply(self, col, val, sigma):
         torch = self.ctx.torch
