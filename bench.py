@@ -96,6 +96,28 @@ def main():
     ms = (t1 - t0) / args.steps * 1e3
     value = prob.NT / (ms * 1e-3)
 
+    # forward + adjoint: generate, apply and the adjoint (gradient of
+    # conj(lambda)^T A sigma wrt node coordinates, k, alpha, beta)
+    sig_t = torch.as_tensor(prob.sigma, dtype=torch.complex128, device="cuda")
+    lam_t = torch.as_tensor(prob.lam, dtype=torch.complex128, device="cuda")
+    grad = torch.empty((prob.N, 3), dtype=torch.complex128, device="cuda")
+    gk = torch.empty(1, dtype=torch.complex128, device="cuda")
+    dab = torch.empty(2, dtype=torch.complex128, device="cuda")
+
+    def fwd_adj():
+        plan.generate(stats=False, **gen)
+        plan.apply(col, val, sig_t)
+        plan.adjoint_into(prob.alpha, prob.beta, prob.k, prob.tol, sig_t, lam_t, grad, gk, dab)
+
+    fwd_adj()
+    torch.cuda.synchronize()
+    nfa = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(nfa):
+        fwd_adj()
+    torch.cuda.synchronize()
+    ms_fa = (time.perf_counter() - t0) / nfa * 1e3
+
     # per-phase durations from HIP events recorded on the library's stream
     phases = {k: 0.0 for k in ("ms_builder", "ms_prep", "ms_self", "ms_near", "ms_weights")}
     st = None
@@ -132,7 +154,9 @@ def main():
                    "targets": prob.NT, "near_pairs": int(prob.near_patch.size),
                    "kernel": "D - ik S", "k": prob.k.real, "tol": prob.tol, "eta": prob.eta,
                    "loosen": 1.0, "global_batch": prob.NT, "parallelism": "single-gpu"},
-        "fwd_adjoint": None,
+        "fwd_adjoint": {"value": prob.NT / (ms_fa * 1e-3), "unit": "target-points/s",
+                        "ms_per_step": ms_fa, "steps": nfa,
+                        "step": "generate + apply + adjoint (gradient wrt nodes, k, alpha, beta)"},
         "phase_ms": phases,
         "gen_stats": {k: st[k] for k in ("near_pairs", "self_pairs", "visits", "checks",
                                          "nonconverged", "max_level")},

@@ -242,6 +242,16 @@ class Plan:
         self.ctx.torch.cuda.synchronize()
         return grad.cpu().numpy(), complex(gk.cpu().numpy()[0]), *[complex(v) for v in dab.cpu().numpy()]
 
+    def adjoint_into(self, alpha, beta, k, tol, sigma, lam, grad, gk, dab, loosen=1.0,
+                     max_depth=16, min_depth=0):
+        """Adjoint into caller-allocated device tensors (no host copies)."""
+        alpha, beta, k = complex(alpha), complex(beta), complex(k)
+        kern = Kernel(alpha.real, alpha.imag, beta.real, beta.imag, k.real, k.imag)
+        prm = Params(float(tol), float(loosen), int(max_depth), 0, 0, 0, 0, int(min_depth))
+        self.ctx._check(self.ctx.L.nfq_adjoint(self.h, C.byref(kern), C.byref(prm), _ptr(sigma),
+                                               _ptr(lam), _ptr(grad), _ptr(gk), _ptr(dab)),
+                        self.ctx.h)
+
     def apply(self, col, val, sigma):
         torch = self.ctx.torch
         y = torch.empty(self.NT, dtype=val.dtype, device=val.device)
