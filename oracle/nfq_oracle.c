@@ -27,8 +27,8 @@
  *    ||I_T - sum I_C||_2 <= tau |T|/|T0|, tau = loosen * eps * d_j / ||V||_2
  *    (scaled tolerance of Section 4.2, eq. for q_j, and Section 4.3).
  *    Subtriangle rule: conical product (Gauss-Jacobi(1,0) x Gauss-Legendre),
- *    n_g points per direction, standing in for the unprinted q-th order
- *    Vioreanu-Rokhlin rule.
+ *    n_g points per direction (8 by default), standing in for the unprinted
+ *    q-th order Vioreanu-Rokhlin rule.
  *  - TRUTH: the same integrals to ~1e-13 relative (20-point rules, tight
  *    tolerance, deep trees) for parity checks.
  *  Self patches (both modes): the target splits T0 into three triangles,
@@ -895,7 +895,8 @@ int orc_pair_weights(const orc_problem *pb, int64_t t, int64_t j, double *out, o
         self_moments(&pt, &kk, pt.ref->uv[2 * l], pt.ref->uv[2 * l + 1],
                      truth ? tau : 0.1 * tau, Imom, st);
     } else {
-        int ng = truth ? 20 : (pb->ng > 0 ? pb->ng : pt.d + 2);
+        /* method mode: 8 x 8 conical product (exact to degree 15) unless set */
+        int ng = truth ? 20 : (pb->ng > 0 ? pb->ng : 8);
         double *rule = malloc(sizeof(double) * 3 * ng * ng);
         if (orc_conical_rule(ng, rule)) { free(rule); return -2; }
         near_moments(&pt, &kk, x, tau, rule, ng * ng, pb->max_depth, truth, Imom, st);
