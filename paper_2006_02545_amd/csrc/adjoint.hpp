@@ -224,7 +224,7 @@ template <int D>
 __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
 {
     using S = PatchShape<D, true>;
-    constexpr int ND = S::ND, NV = S::NV, W = S::W, PL = S::PL, GS = S::GS;
+    constexpr int ND = S::ND, W = S::W, PL = S::PL, GS = S::GS, G0 = S::G0;
     constexpr int NG = 6 * ND;  // real components of the chart-coefficient gradient
     const PatchArgs &a = aa.pa;
     __shared__ double s_geo[256 * GS];
@@ -262,8 +262,9 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
         for (int k = tid; k < 64 * 12; k += 256) (&s_t[0][0])[k] = 0.0;
         for (int k = tid; k < 4 * NG; k += 256) (&s_gw[0][0])[k] = 0.0;
         if (tid < 64)
-            node_geometry<D>(cf, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, a.rule[3 * tid], a.rule[3 * tid + 1],
-                             a.rule[3 * tid + 2], s_geo + tid * GS);
+            node_geometry<D, true>(cf, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, a.rule[3 * tid],
+                                   a.rule[3 * tid + 1], a.rule[3 * tid + 2], s_geo + tid * GS,
+                                   tid & 15);
         __syncthreads();
         // root moments (as in the forward)
         for (int s = wv; s < count; s += 4) {
@@ -273,13 +274,9 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
             for (int v = 0; v < W; ++v) acc[v] = 0.0;
             const double *g = s_geo + lane * GS;
             double fr, fi;
-            kern_node(a.kern, a.helm, x, g, fr, fi, singular);
-#pragma unroll
-            for (int m = 0; m < ND; ++m) {
-                acc[2 * m] = fr * g[7 + m];
-                acc[2 * m + 1] = fi * g[7 + m];
-            }
-            reduce_scatter16<W>(acc, lane);
+            kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
+            mac_node<D, true>(acc, g, fr, fi);
+            rot_reduce16<PL>(acc);
 #pragma unroll
             for (int i = 0; i < PL; ++i) {
                 acc[i] += __shfl_xor(acc[i], 16, 64);
@@ -326,8 +323,8 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                 else if (c == 1) { Ax = abx; Ay = aby; Bx = bx; By = by; Cx = bcx; Cy = bcy; }
                 else if (c == 2) { Ax = cax; Ay = cay; Bx = bcx; By = bcy; Cx = cx; Cy = cy; }
                 else { Ax = bcx; Ay = bcy; Bx = cax; By = cay; Cx = abx; Cy = aby; }
-                node_geometry<D>(cf, Ax, Ay, Bx, By, Cx, Cy, a.rule[3 * q], a.rule[3 * q + 1],
-                                 a.rule[3 * q + 2] * area, s_geo + tid * GS);
+                node_geometry<D, true>(cf, Ax, Ay, Bx, By, Cx, Cy, a.rule[3 * q], a.rule[3 * q + 1],
+                                       a.rule[3 * q + 2] * area, s_geo + tid * GS, tid & 15);
             }
             __syncthreads();
             const double thr = tau * __builtin_ldexp(1.0, -2 * e.level);
@@ -358,23 +355,20 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                 for (int i = 0; i < 4; ++i) {
                     const double *g = s_geo + (grp16 * 64 + l16 + 16 * i) * GS;
                     double fr, fi;
-                    kern_node(a.kern, a.helm, x, g, fr, fi, singular);
-#pragma unroll
-                    for (int m = 0; m < ND; ++m) {
-                        acc[2 * m] = __builtin_fma(fr, g[7 + m], acc[2 * m]);
-                        acc[2 * m + 1] = __builtin_fma(fi, g[7 + m], acc[2 * m + 1]);
-                    }
+                    kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
+                    mac_node<D, true>(acc, g, fr, fi);
                 }
-                reduce_scatter16<W>(acc, lane);
+                rot_reduce16<PL>(acc);
+                // the forward's test, in the same arithmetic
                 double e2 = 0.0;
 #pragma unroll
                 for (int i = 0; i < PL; ++i) {
                     double v = acc[i] + __shfl_xor(acc[i], 16, 64);
                     v += __shfl_xor(v, 32, 64);
                     const double df = v - IT[i];
-                    e2 += grp16 == 0 ? df * df : 0.0;
+                    e2 = __builtin_fma(df, df, e2);
                 }
-                const double err2 = wave_sum(e2);
+                const double err2 = lane0(row_sum16(e2));
                 bool accept = err2 <= thr * thr && L + 1 >= a.min_depth;
                 if (!accept && L + 1 >= a.max_depth) accept = true;
                 if (accept) {

@@ -553,6 +553,8 @@ __global__ __launch_bounds__((64 * QuadShape<D, CPLX>::WPB)) void k_near(QuadArg
 
 // -------------------------------------------------------- self quadrature
 
+constexpr int kPanW = 9;
+
 template <int D, bool CPLX>
 struct SelfShape {
     static constexpr int ND = nd_of(D);
@@ -573,6 +575,8 @@ __global__ __launch_bounds__((64 * SelfShape<D, CPLX>::WPB)) void k_self(QuadArg
     constexpr int ND = S::ND, NV = S::NV, RP = S::RP, WPB = S::WPB;
     constexpr int NL = (NV + 63) / 64;
     __shared__ double s_stage[WPB][64 * RP];
+    // per wavefront: up to 6 panels x (A, E, mu, h/L, det, xi_a, xi_b)
+    __shared__ double s_pan[WPB][6][kPanW];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double *stage = s_stage[wv];
     const int64_t wave_id = (int64_t)blockIdx.x * WPB + wv;
@@ -604,7 +608,6 @@ __global__ __launch_bounds__((64 * SelfShape<D, CPLX>::WPB)) void k_self(QuadArg
         // distance from t to the edge point is sqrt(h^2 + (lam - mu)^2 L^2);
         // lam = mu + (h/L) sinh(xi) makes the angular integrand smooth.  The
         // panel is split at the foot (xi = 0) when it lies inside the edge.
-        double pA[6][2], pE[6][2], pmu[6], phl[6], pdet[6], pxa[6], pxb[6];
         int npan = 0;
         const double Pv[3][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}};
 #pragma unroll
@@ -623,13 +626,20 @@ __global__ __launch_bounds__((64 * SelfShape<D, CPLX>::WPB)) void k_self(QuadArg
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
                 if (half == 1 && !split) break;
-                pA[npan][0] = Ax; pA[npan][1] = Ay; pE[npan][0] = Ex; pE[npan][1] = Ey;
-                pmu[npan] = mu; phl[npan] = h / L; pdet[npan] = det;
-                pxa[npan] = split ? (half == 0 ? x0 : 0.0) : x0;
-                pxb[npan] = split ? (half == 0 ? 0.0 : x1) : x1;
+                // the values are uniform over the wavefront: one lane stores them
+                if (lane == 0) {
+                    double *pp = s_pan[wv][npan];
+                    pp[0] = Ax; pp[1] = Ay; pp[2] = Ex; pp[3] = Ey;
+                    pp[4] = mu; pp[5] = h / L; pp[6] = det;
+                    pp[7] = split ? (half == 0 ? x0 : 0.0) : x0;
+                    pp[8] = split ? (half == 0 ? 0.0 : x1) : x1;
+                }
                 ++npan;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         double acc[NL];
 #pragma unroll
         for (int k = 0; k < NL; ++k) acc[k] = 0.0;
@@ -645,13 +655,9 @@ __global__ __launch_bounds__((64 * SelfShape<D, CPLX>::WPB)) void k_self(QuadArg
                 const int pi = q / per_panel;
                 const int rem = q - pi * per_panel;
                 const int ia = rem / nr, ir = rem - ia * nr;
-                double Ax = 0, Ay = 0, Ex = 0, Ey = 0, mu = 0, hl = 0, det = 0, xa = 0, xb = 0;
-#pragma unroll
-                for (int k = 0; k < 6; ++k)
-                    if (k == pi) {
-                        Ax = pA[k][0]; Ay = pA[k][1]; Ex = pE[k][0]; Ey = pE[k][1]; mu = pmu[k];
-                        hl = phl[k]; det = pdet[k]; xa = pxa[k]; xb = pxb[k];
-                    }
+                const double *pp = s_pan[wv][pi];
+                const double Ax = pp[0], Ay = pp[1], Ex = pp[2], Ey = pp[3], mu = pp[4];
+                const double hl = pp[5], det = pp[6], xa = pp[7], xb = pp[8];
                 const double xi = xa + (xb - xa) * a.gla[2 * ia];
                 const double lam = mu + hl * sinh(xi);
                 const double dlam = hl * cosh(xi) * (xb - xa) * a.gla[2 * ia + 1];

@@ -27,17 +27,32 @@ namespace nfq {
 
 constexpr int kGroupStack = 3 * kMaxDepth + 8;
 
+// Moments are reduced over the 16 lanes of a row by rotations (DPP row_ror):
+// the ND basis functions are padded to KS = 16 R slots, grouped into 16 units
+// of R; the lane with row index l stores unit (l + p) mod 16 in its slot
+// group p, so that the reduce-scatter needs no per-lane selects and leaves
+// unit l (R functions, times 1 or 2 for complex) on lane l.
 template <int D, bool CPLX>
 struct PatchShape {
     static constexpr int ND = nd_of(D);
-    static constexpr int NV = CPLX ? 2 * ND : ND;
-    static constexpr int W = (NV + 15) / 16 * 16;   // padded components
-    static constexpr int PL = W / 16;                // components per lane after the reduce-scatter
-    static constexpr int GS = (7 + ND) | 1;          // LDS doubles per node (odd pitch)
+    static constexpr int C = CPLX ? 2 : 1;           // doubles per moment
+    static constexpr int NV = C * ND;                // doubles per moment vector
+    static constexpr int R = (ND + 15) / 16;         // basis functions per unit
+    static constexpr int KS = 16 * R;                // basis slots per node
+    static constexpr int PL = R * C;                 // doubles per lane after the reduce-scatter
+    static constexpr int W = 16 * PL;                // doubles per lane before it
+    static constexpr int GS = (KS + 7) | 1;          // LDS doubles per node (odd pitch)
+    static constexpr int G0 = KS;                    // y, n w, J w follow the basis slots
     // per-target totals kept in LDS when they fit beside the geometry
     static constexpr bool TOT_LDS = (64 * NV + 256 * GS) * 8 <= 140 * 1024;
     static constexpr int TOTN = TOT_LDS ? 64 * NV : 1;
 };
+
+// Doubles per lane of the moment vectors for degree d (host sizing).
+inline constexpr int patch_w(int d, bool cplx)
+{
+    return 16 * ((nd_of(d) + 15) / 16) * (cplx ? 2 : 1);
+}
 
 struct PatchArgs {
     Problem pb;
@@ -61,34 +76,62 @@ struct PatchArgs {
     unsigned long long *stats;
 };
 
-// 16-lane reduce-scatter: on entry acc[W] holds this lane's partial sums;
-// on exit acc[0..PL) holds components [PL * (lane & 15), PL * (lane & 15) + PL)
-// summed over the 16 lanes of the lane's group.
-template <int W>
-__device__ __forceinline__ void reduce_scatter16(double *acc, int lane)
+// Value of lane (l - N) mod 16 of the same row (DPP row rotation).
+template <int N>
+__device__ __forceinline__ double row_ror(double x)
 {
-#pragma unroll
-    for (int step = 0; step < 4; ++step) {
-        const int m = 8 >> step;
-        const int w = W >> (step + 1);
-        const bool hi = (lane & m) != 0;
-#pragma unroll
-        for (int i = 0; i < w; ++i) {
-            const double lo_v = acc[i], hi_v = acc[i + w];
-            const double send = hi ? lo_v : hi_v;
-            const double keep = hi ? hi_v : lo_v;
-            acc[i] = keep + __shfl_xor(send, m, 64);
-        }
-    }
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, 0x120 + N, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), 0x120 + N, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
-// Geometry of one rule node of triangle (A, B, C) into LDS: y, n w, J w, K.
-template <int D>
+// Reduce-scatter over the 16 lanes of each row for the rotated slot layout:
+// on entry acc[W] holds this lane's partial sums with slot group p carrying
+// unit (l + p) mod 16; on exit acc[0..PL) holds unit l summed over the row.
+template <int PL>
+__device__ __forceinline__ void rot_reduce16(double *acc)
+{
+#pragma unroll
+    for (int i = 0; i < 8 * PL; ++i) acc[i] += row_ror<8>(acc[i + 8 * PL]);
+#pragma unroll
+    for (int i = 0; i < 4 * PL; ++i) acc[i] += row_ror<4>(acc[i + 4 * PL]);
+#pragma unroll
+    for (int i = 0; i < 2 * PL; ++i) acc[i] += row_ror<2>(acc[i + 2 * PL]);
+#pragma unroll
+    for (int i = 0; i < PL; ++i) acc[i] += row_ror<1>(acc[i + PL]);
+}
+
+// Sum over the 16 lanes of each row, into every lane of the row.
+__device__ __forceinline__ double row_sum16(double v)
+{
+    v += row_ror<8>(v);
+    v += row_ror<4>(v);
+    v += row_ror<2>(v);
+    v += row_ror<1>(v);
+    return v;
+}
+
+// Wave-uniform copy of lane 0's value.
+__device__ __forceinline__ double lane0(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Geometry of one rule node of triangle (A, B, C) into LDS row g: basis
+// values in the rotated slot order of reader row lane l16 (padding slots 0),
+// then y, n w, J w.
+template <int D, bool CPLX>
 __device__ __forceinline__ void node_geometry(const double *cf, double Ax, double Ay, double Bx,
                                               double By, double Cx, double Cy, double ru, double rv,
-                                              double wgt, double *g)
+                                              double wgt, double *g, int l16)
 {
-    constexpr int ND = nd_of(D);
+    using S = PatchShape<D, CPLX>;
+    constexpr int ND = S::ND, R = S::R, G0 = S::G0;
+    asm volatile("" : "+v"(ru));
     const double u = Ax + ru * (Bx - Ax) + rv * (Cx - Ax);
     const double v = Ay + ru * (By - Ay) + rv * (Cy - Ay);
     double K[ND], X[3], Xu[3], Xv[3];
@@ -96,17 +139,42 @@ __device__ __forceinline__ void node_geometry(const double *cf, double Ax, doubl
     const double n0 = Xu[1] * Xv[2] - Xu[2] * Xv[1];
     const double n1 = Xu[2] * Xv[0] - Xu[0] * Xv[2];
     const double n2 = Xu[0] * Xv[1] - Xu[1] * Xv[0];
-    g[0] = X[0]; g[1] = X[1]; g[2] = X[2];
-    g[3] = n0 * wgt; g[4] = n1 * wgt; g[5] = n2 * wgt;
-    g[6] = __builtin_sqrt(n0 * n0 + n1 * n1 + n2 * n2) * wgt;
+    g[G0 + 0] = X[0]; g[G0 + 1] = X[1]; g[G0 + 2] = X[2];
+    g[G0 + 3] = n0 * wgt; g[G0 + 4] = n1 * wgt; g[G0 + 5] = n2 * wgt;
+    g[G0 + 6] = __builtin_sqrt(n0 * n0 + n1 * n1 + n2 * n2) * wgt;
+    int rot = (16 - l16) & 15;
+    // keep the slot addresses local to this call (hoisting them out of the
+    // caller's loops would pin 16 R registers for the whole kernel)
+    asm volatile("" : "+v"(rot));
 #pragma unroll
-    for (int a = 0; a < ND; ++a) g[7 + a] = K[a];
+    for (int m = 0; m < 16 * R; ++m) {
+        const int unit = m / R, r = m - unit * R;
+        g[((unit + rot) & 15) * R + r] = m < ND ? K[m] : 0.0;
+    }
+}
+
+// acc += (fr, fi) times the basis slots of node row g.
+template <int D, bool CPLX>
+__device__ __forceinline__ void mac_node(double *acc, const double *g, double fr, double fi)
+{
+    using S = PatchShape<D, CPLX>;
+#pragma unroll
+    for (int m = 0; m < S::KS; ++m) {
+        const double kv = g[m];
+        if (CPLX) {
+            acc[2 * m] = __builtin_fma(fr, kv, acc[2 * m]);
+            acc[2 * m + 1] = __builtin_fma(fi, kv, acc[2 * m + 1]);
+        } else {
+            acc[m] = __builtin_fma(fr, kv, acc[m]);
+        }
+    }
 }
 
 // Weighted kernel value at a node whose geometry g carries n w and J w.
 __device__ __forceinline__ void kern_node(const Kern &k, bool helm, const double x[3],
                                           const double *g, double &fr, double &fi, int &singular)
 {
+    // g points at the node's y, n w, J w
     const double dx = x[0] - g[0], dy = x[1] - g[1], dz = x[2] - g[2];
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (r2 == 0.0) singular = 1;
@@ -145,13 +213,14 @@ template <int D, bool CPLX>
 __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs a)
 {
     using S = PatchShape<D, CPLX>;
-    constexpr int ND = S::ND, NV = S::NV, W = S::W, PL = S::PL, GS = S::GS;
-    constexpr int C = CPLX ? 2 : 1;
+    constexpr int NV = S::NV, W = S::W, PL = S::PL, GS = S::GS, G0 = S::G0;
+    constexpr int C = S::C;
     __shared__ double s_geo[256 * GS];
     __shared__ double s_tot[S::TOTN];
     __shared__ GroupEntry s_stack[kGroupStack];
     __shared__ double s_x[64][3];
     __shared__ int64_t s_off[64];
+    __shared__ double s_cf[3 * S::ND];
     __shared__ unsigned long long s_fail;
     __shared__ int s_sp;
 
@@ -166,7 +235,9 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
     for (int64_t it = blockIdx.x; it < a.item_count; it += gridDim.x) {
         const int32_t *item = a.items + 3 * (a.item_seg + it);
         const int j = item[0], start = item[1], count = item[2];
-        const double *cf = a.coef + 3 * a.pb.node_ptr[j];
+        // chart coefficients in LDS, read at every use (kept out of registers)
+        for (int k = tid; k < 3 * S::ND; k += 256) s_cf[k] = a.coef[3 * a.pb.node_ptr[j] + k];
+        const double *cf = s_cf;
         const double tau = a.tau[j];
         if (tid < count) {
             const int p = a.plist[start + tid];
@@ -182,9 +253,10 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
         if (S::TOT_LDS)
             for (int k = tid; k < 64 * NV; k += 256) s_tot[k] = 0.0;
         if (tid < 64) {
-            // root geometry: node tid of the rule on T0
-            node_geometry<D>(cf, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, a.rule[3 * tid], a.rule[3 * tid + 1],
-                             a.rule[3 * tid + 2], s_geo + tid * GS);
+            // root geometry: node tid of the rule on T0, read by lane tid
+            node_geometry<D, CPLX>(cf, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, a.rule[3 * tid],
+                                   a.rule[3 * tid + 1], a.rule[3 * tid + 2], s_geo + tid * GS,
+                                   tid & 15);
         }
         __syncthreads();
         // root moments of every target: one node per lane
@@ -195,14 +267,9 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
             for (int v = 0; v < W; ++v) acc[v] = 0.0;
             const double *g = s_geo + lane * GS;
             double fr, fi;
-            kern_node(a.kern, a.helm, x, g, fr, fi, singular);
-#pragma unroll
-            for (int m = 0; m < ND; ++m) {
-                const double k = g[7 + m];
-                if (CPLX) { acc[2 * m] = fr * k; acc[2 * m + 1] = fi * k; }
-                else acc[m] = fr * k;
-            }
-            reduce_scatter16<W>(acc, lane);
+            kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
+            mac_node<D, CPLX>(acc, g, fr, fi);
+            rot_reduce16<PL>(acc);
 #pragma unroll
             for (int i = 0; i < PL; ++i) {
                 acc[i] += __shfl_xor(acc[i], 16, 64);
@@ -233,7 +300,8 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                 s_sp = s_sp - 1;
                 s_fail = 0ull;
             }
-            // children geometry: thread tid -> child tid / 64, node tid % 64
+            // children geometry: thread tid -> child tid / 64, node tid % 64,
+            // read by row lane tid % 16
             const double ax = e.tri[0], ay = e.tri[1], bx = e.tri[2], by = e.tri[3];
             const double cx = e.tri[4], cy = e.tri[5];
             const double abx = 0.5 * (ax + bx), aby = 0.5 * (ay + by);
@@ -247,8 +315,8 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                 else if (c == 2) { Ax = cax; Ay = cay; Bx = bcx; By = bcy; Cx = cx; Cy = cy; }
                 else { Ax = bcx; Ay = bcy; Bx = cax; By = cay; Cx = abx; Cy = aby; }
                 const double area = __builtin_ldexp(1.0, -2 * (e.level + 1));
-                node_geometry<D>(cf, Ax, Ay, Bx, By, Cx, Cy, a.rule[3 * q], a.rule[3 * q + 1],
-                                 a.rule[3 * q + 2] * area, s_geo + tid * GS);
+                node_geometry<D, CPLX>(cf, Ax, Ay, Bx, By, Cx, Cy, a.rule[3 * q], a.rule[3 * q + 1],
+                                       a.rule[3 * q + 2] * area, s_geo + tid * GS, tid & 15);
             }
             __syncthreads();
             const double thr = tau * __builtin_ldexp(1.0, -2 * e.level);
@@ -275,21 +343,12 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                 for (int i = 0; i < 4; ++i) {
                     const double *g = s_geo + (grp16 * 64 + l16 + 16 * i) * GS;
                     double fr, fi;
-                    kern_node(a.kern, a.helm, x, g, fr, fi, singular);
-#pragma unroll
-                    for (int m = 0; m < ND; ++m) {
-                        const double kv = g[7 + m];
-                        if (CPLX) {
-                            acc[2 * m] = __builtin_fma(fr, kv, acc[2 * m]);
-                            acc[2 * m + 1] = __builtin_fma(fi, kv, acc[2 * m + 1]);
-                        } else {
-                            acc[m] = __builtin_fma(fr, kv, acc[m]);
-                        }
-                    }
+                    kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
+                    mac_node<D, CPLX>(acc, g, fr, fi);
                 }
-                reduce_scatter16<W>(acc, lane);
-                // acc[0..PL): components of child grp16's moments; the sum
-                // over the four children by two more exchanges
+                rot_reduce16<PL>(acc);
+                // acc[0..PL): unit l16 of child grp16's moments; the sum over
+                // the four children by two more exchanges
                 double Ssum[PL];
                 double e2 = 0.0;
 #pragma unroll
@@ -298,9 +357,10 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                     v += __shfl_xor(v, 32, 64);
                     Ssum[i] = v;
                     const double df = v - IT[i];
-                    e2 += grp16 == 0 ? df * df : 0.0;
+                    e2 = __builtin_fma(df, df, e2);
                 }
-                const double err2 = wave_sum(e2);
+                // every row holds the same children sum: row 0's total decides
+                const double err2 = lane0(row_sum16(e2));
                 ++st_checks;
                 st_visits += 4;
                 const bool ok = err2 <= thr * thr;

@@ -390,7 +390,7 @@ static nfq_status prepare(nfq_plan *pl, const nfq_kernel *kern, const nfq_params
     qa.stats = pl->stats;
     if (!per_pair) {
         // per-slot moment storage of the patch kernel: [max_depth + 1][4][64][W]
-        const int64_t wmax = (2 * nd_of(pl->max_degree) + 15) / 16 * 16;
+        const int64_t wmax = patch_w(pl->max_degree, true);
         const int64_t need = (int64_t)(prm->max_depth + 1) * 4 * 64 * wmax;
         if (need > pl->mom_slot || !pl->mom) {
             if (pl->mom) (void)hipFree(pl->mom);
