@@ -234,6 +234,7 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
     __shared__ int32_t s_pair[64];
     __shared__ double s_t[64][12];
     __shared__ double s_gw[4][NG];
+    __shared__ double s_cm[4 * W];
     __shared__ unsigned long long s_fail;
     __shared__ int s_sp;
 
@@ -242,6 +243,7 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
     double *mom = a.mom + (int64_t)blockIdx.x * a.mom_slot;
     auto mptr = [&](int L, int c, int s) { return mom + ((int64_t)(L * 4 + c) * 64 + s) * W; };
     int singular = 0;
+    unsigned ngroup = 0;
 
     for (int64_t it = blockIdx.x; it < a.item_count; it += gridDim.x) {
         const int32_t *item = a.items + 3 * (a.item_seg + it);
@@ -335,12 +337,41 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
             else if (grp16 == 1) { Ax = abx; Ay = aby; Bx = bx; By = by; Cx = bcx; Cy = bcy; }
             else if (grp16 == 2) { Ax = cax; Ay = cay; Bx = bcx; By = bcy; Cx = cx; Cy = cy; }
             else { Ax = bcx; Ay = bcy; Bx = cax; By = cay; Cx = abx; Cy = aby; }
-            unsigned long long mk = e.mask;
-            int k = 0;
-            while (mk) {
-                const int s = __builtin_ctzll(mk);
-                mk &= mk - 1ull;
-                if ((k++ & 3) != wv) continue;
+            // gradient pass for target s over the 256 children nodes, 4 per lane
+            auto grad_pass = [&](int s, const double *x) {
+                const double lr = s_lam[s][0], li = s_lam[s][1];
+                double T12[12];
+#pragma unroll
+                for (int v = 0; v < 12; ++v) T12[v] = 0.0;
+#pragma unroll 1
+                for (int i = 0; i < 4; ++i) {
+                    const int q = l16 + 16 * i;
+                    const double ru = a.rule[3 * q], rv = a.rule[3 * q + 1];
+                    const double wq = a.rule[3 * q + 2] * area;
+                    const double u = Ax + ru * (Bx - Ax) + rv * (Cx - Ax);
+                    const double v = Ay + ru * (By - Ay) + rv * (Cy - Ay);
+                    double K[ND], Ku[ND], Kv[ND], X[3], Xu[3], Xv[3];
+                    chart_eval_d<D>(cf, u, v, K, Ku, Kv, X, Xu, Xv);
+                    const double n[3] = {Xu[1] * Xv[2] - Xu[2] * Xv[1], Xu[2] * Xv[0] - Xu[0] * Xv[2],
+                                         Xu[0] * Xv[1] - Xu[1] * Xv[0]};
+                    double sgr, sgi, rhr, rhi;
+                    sigma_at<ND>(sc, K, sgr, sgi);
+                    cmul(lr, li, sgr, sgi, rhr, rhi);
+                    NodeGrad gg;
+                    node_grad(a.kern, x, X, n, wq, rhr, rhi, gg);
+                    accumulate_node<ND>(gg, K, Ku, Kv, Xu, Xv, GC, T12);
+                }
+#pragma unroll
+                for (int v = 0; v < 12; ++v) {
+                    const double tv = wave_sum(T12[v]);
+                    if (lane == 0) s_t[s][v] += tv;
+                }
+            };
+            // the forward's work split and test, in the same arithmetic
+            const int kofs = (int)((ngroup++ + blockIdx.x) & 3);
+            if (__builtin_popcountll(e.mask) == 1) {
+                const int s = __builtin_ctzll(e.mask);
+                const bool mine = wv == kofs;
                 const double x[3] = {s_x[s][0], s_x[s][1], s_x[s][2]};
                 double IT[PL];
                 {
@@ -351,20 +382,27 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                 double acc[W];
 #pragma unroll
                 for (int v = 0; v < W; ++v) acc[v] = 0.0;
-#pragma unroll 1
-                for (int i = 0; i < 4; ++i) {
-                    const double *g = s_geo + (grp16 * 64 + l16 + 16 * i) * GS;
+                {
+                    const double *g = s_geo + tid * GS;
                     double fr, fi;
                     kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
                     mac_node<D, true>(acc, g, fr, fi);
                 }
                 rot_reduce16<PL>(acc);
-                // the forward's test, in the same arithmetic
-                double e2 = 0.0;
+                double cm[PL];
 #pragma unroll
                 for (int i = 0; i < PL; ++i) {
                     double v = acc[i] + __shfl_xor(acc[i], 16, 64);
                     v += __shfl_xor(v, 32, 64);
+                    cm[i] = v;
+                    if (grp16 == 0) s_cm[wv * W + PL * l16 + i] = v;
+                }
+                __syncthreads();
+                double e2 = 0.0;
+#pragma unroll
+                for (int i = 0; i < PL; ++i) {
+                    const int o = PL * l16 + i;
+                    const double v = (s_cm[o] + s_cm[W + o]) + (s_cm[2 * W + o] + s_cm[3 * W + o]);
                     const double df = v - IT[i];
                     e2 = __builtin_fma(df, df, e2);
                 }
@@ -372,39 +410,60 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                 bool accept = err2 <= thr * thr && L + 1 >= a.min_depth;
                 if (!accept && L + 1 >= a.max_depth) accept = true;
                 if (accept) {
-                    // gradient pass over the 256 children nodes, 4 per lane
-                    const double lr = s_lam[s][0], li = s_lam[s][1];
-                    double T12[12];
+                    if (mine) grad_pass(s, x);
+                } else {
+                        if (grp16 == 0) {
+                            double *dst = mptr(L + 1, wv, s);
 #pragma unroll
-                    for (int v = 0; v < 12; ++v) T12[v] = 0.0;
-#pragma unroll 1
-                    for (int i = 0; i < 4; ++i) {
-                        const int q = l16 + 16 * i;
-                        const double ru = a.rule[3 * q], rv = a.rule[3 * q + 1];
-                        const double wq = a.rule[3 * q + 2] * area;
-                        const double u = Ax + ru * (Bx - Ax) + rv * (Cx - Ax);
-                        const double v = Ay + ru * (By - Ay) + rv * (Cy - Ay);
-                        double K[ND], Ku[ND], Kv[ND], X[3], Xu[3], Xv[3];
-                        chart_eval_d<D>(cf, u, v, K, Ku, Kv, X, Xu, Xv);
-                        const double n[3] = {Xu[1] * Xv[2] - Xu[2] * Xv[1], Xu[2] * Xv[0] - Xu[0] * Xv[2],
-                                             Xu[0] * Xv[1] - Xu[1] * Xv[0]};
-                        double sgr, sgi, rhr, rhi;
-                        sigma_at<ND>(sc, K, sgr, sgi);
-                        cmul(lr, li, sgr, sgi, rhr, rhi);
-                        NodeGrad gg;
-                        node_grad(a.kern, x, X, n, wq, rhr, rhi, gg);
-                        accumulate_node<ND>(gg, K, Ku, Kv, Xu, Xv, GC, T12);
-                    }
-#pragma unroll
-                    for (int v = 0; v < 12; ++v) {
-                        const double tv = wave_sum(T12[v]);
-                        if (lane == 0) s_t[s][v] += tv;
+                            for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = cm[i];
+                        }
+                        if (tid == 0) s_fail = 1ull << s;
                     }
                 } else {
-                    double *dst = mptr(L + 1, grp16, s);
+                unsigned long long mk = e.mask;
+                int k = kofs;
+                while (mk) {
+                    const int s = __builtin_ctzll(mk);
+                    mk &= mk - 1ull;
+                    if ((k++ & 3) != wv) continue;
+                    const double x[3] = {s_x[s][0], s_x[s][1], s_x[s][2]};
+                    double IT[PL];
+                    {
+                        const double *src = mptr(L, e.child, s);
 #pragma unroll
-                    for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = acc[i];
-                    if (lane == 0) atomicOr(&s_fail, 1ull << s);
+                        for (int i = 0; i < PL; ++i) IT[i] = src[PL * l16 + i];
+                    }
+                    double acc[W];
+#pragma unroll
+                    for (int v = 0; v < W; ++v) acc[v] = 0.0;
+#pragma unroll 1
+                    for (int i = 0; i < 4; ++i) {
+                        const double *g = s_geo + (grp16 * 64 + l16 + 16 * i) * GS;
+                        double fr, fi;
+                        kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
+                        mac_node<D, true>(acc, g, fr, fi);
+                    }
+                    rot_reduce16<PL>(acc);
+                    // the forward's test, in the same arithmetic
+                    double e2 = 0.0;
+#pragma unroll
+                    for (int i = 0; i < PL; ++i) {
+                        double v = acc[i] + __shfl_xor(acc[i], 16, 64);
+                        v += __shfl_xor(v, 32, 64);
+                        const double df = v - IT[i];
+                        e2 = __builtin_fma(df, df, e2);
+                    }
+                    const double err2 = lane0(row_sum16(e2));
+                    bool accept = err2 <= thr * thr && L + 1 >= a.min_depth;
+                    if (!accept && L + 1 >= a.max_depth) accept = true;
+                    if (accept) {
+                        grad_pass(s, x);
+                    } else {
+                        double *dst = mptr(L + 1, grp16, s);
+#pragma unroll
+                        for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = acc[i];
+                        if (lane == 0) atomicOr(&s_fail, 1ull << s);
+                    }
                 }
             }
             __syncthreads();

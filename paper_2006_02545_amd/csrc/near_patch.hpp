@@ -221,6 +221,7 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
     __shared__ double s_x[64][3];
     __shared__ int64_t s_off[64];
     __shared__ double s_cf[3 * S::ND];
+    __shared__ double s_cm[4 * W];
     __shared__ unsigned long long s_fail;
     __shared__ int s_sp;
 
@@ -231,6 +232,7 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
     auto mptr = [&](int L, int c, int s) { return mom + ((int64_t)(L * 4 + c) * 64 + s) * W; };
     unsigned long long st_visits = 0, st_checks = 0, st_nonconv = 0, st_maxlev = 0, st_pairs = 0;
     int singular = 0;
+    unsigned ngroup = 0;
 
     for (int64_t it = blockIdx.x; it < a.item_count; it += gridDim.x) {
         const int32_t *item = a.items + 3 * (a.item_seg + it);
@@ -321,15 +323,15 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
             __syncthreads();
             const double thr = tau * __builtin_ldexp(1.0, -2 * e.level);
             const int L = e.level;
-            // targets of the mask, the k-th set bit to wavefront k % 4
-            unsigned long long mk = e.mask;
-            int k = 0;
-            while (mk) {
-                const int s = __builtin_ctzll(mk);
-                mk &= mk - 1ull;
-                if ((k++ & 3) != wv) continue;
+            // the wavefront that takes the first target of this group (varies
+            // from group to group to spread the work over the SIMDs)
+            const int kofs = (int)((ngroup++ + blockIdx.x) & 3);
+            if (__builtin_popcountll(e.mask) == 1) {
+                // one target: the four wavefronts take one child each, one
+                // node per lane; children moments meet in LDS
+                const int s = __builtin_ctzll(e.mask);
+                const bool mine = wv == kofs;
                 const double x[3] = {s_x[s][0], s_x[s][1], s_x[s][2]};
-                // parent moments: loads issued before the node work
                 double IT[PL];
                 {
                     const double *src = mptr(L, e.child, s);
@@ -339,38 +341,45 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                 double acc[W];
 #pragma unroll
                 for (int v = 0; v < W; ++v) acc[v] = 0.0;
-#pragma unroll 1
-                for (int i = 0; i < 4; ++i) {
-                    const double *g = s_geo + (grp16 * 64 + l16 + 16 * i) * GS;
+                {
+                    const double *g = s_geo + tid * GS;
                     double fr, fi;
                     kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
                     mac_node<D, CPLX>(acc, g, fr, fi);
                 }
                 rot_reduce16<PL>(acc);
-                // acc[0..PL): unit l16 of child grp16's moments; the sum over
-                // the four children by two more exchanges
-                double Ssum[PL];
-                double e2 = 0.0;
+                double cm[PL];
 #pragma unroll
                 for (int i = 0; i < PL; ++i) {
                     double v = acc[i] + __shfl_xor(acc[i], 16, 64);
                     v += __shfl_xor(v, 32, 64);
+                    cm[i] = v;
+                    if (grp16 == 0) s_cm[wv * W + PL * l16 + i] = v;
+                }
+                __syncthreads();
+                double Ssum[PL];
+                double e2 = 0.0;
+#pragma unroll
+                for (int i = 0; i < PL; ++i) {
+                    const int o = PL * l16 + i;
+                    const double v = (s_cm[o] + s_cm[W + o]) + (s_cm[2 * W + o] + s_cm[3 * W + o]);
                     Ssum[i] = v;
                     const double df = v - IT[i];
                     e2 = __builtin_fma(df, df, e2);
                 }
-                // every row holds the same children sum: row 0's total decides
                 const double err2 = lane0(row_sum16(e2));
-                ++st_checks;
-                st_visits += 4;
+                if (mine) {
+                    ++st_checks;
+                    st_visits += 4;
+                }
                 const bool ok = err2 <= thr * thr;
                 bool accept = ok && L + 1 >= a.min_depth;
                 if (!accept && L + 1 >= a.max_depth) {
                     accept = true;
-                    if (!ok) ++st_nonconv;
+                    if (!ok && mine) ++st_nonconv;
                 }
                 if (accept) {
-                    if (grp16 == 0) {
+                    if (mine && grp16 == 0) {
                         double *dst = S::TOT_LDS ? s_tot + s * NV : a.val + C * s_off[s];
 #pragma unroll
                         for (int i = 0; i < PL; ++i) {
@@ -378,12 +387,80 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                             if (comp < NV) dst[comp] += Ssum[i];
                         }
                     }
-                    if ((unsigned long long)(L + 1) > st_maxlev) st_maxlev = L + 1;
+                    if (mine && (unsigned long long)(L + 1) > st_maxlev) st_maxlev = L + 1;
                 } else {
-                    double *dst = mptr(L + 1, grp16, s);
+                        if (grp16 == 0) {
+                            double *dst = mptr(L + 1, wv, s);
 #pragma unroll
-                    for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = acc[i];
-                    if (lane == 0) atomicOr(&s_fail, 1ull << s);
+                            for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = cm[i];
+                        }
+                        if (tid == 0) s_fail = 1ull << s;
+                    }
+                } else {
+                // targets of the mask, the k-th set bit to wavefront (k + kofs) % 4
+                unsigned long long mk = e.mask;
+                int k = kofs;
+                while (mk) {
+                    const int s = __builtin_ctzll(mk);
+                    mk &= mk - 1ull;
+                    if ((k++ & 3) != wv) continue;
+                    const double x[3] = {s_x[s][0], s_x[s][1], s_x[s][2]};
+                    // parent moments: loads issued before the node work
+                    double IT[PL];
+                    {
+                        const double *src = mptr(L, e.child, s);
+#pragma unroll
+                        for (int i = 0; i < PL; ++i) IT[i] = src[PL * l16 + i];
+                    }
+                    double acc[W];
+#pragma unroll
+                    for (int v = 0; v < W; ++v) acc[v] = 0.0;
+#pragma unroll 1
+                    for (int i = 0; i < 4; ++i) {
+                        const double *g = s_geo + (grp16 * 64 + l16 + 16 * i) * GS;
+                        double fr, fi;
+                        kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
+                        mac_node<D, CPLX>(acc, g, fr, fi);
+                    }
+                    rot_reduce16<PL>(acc);
+                    // acc[0..PL): unit l16 of child grp16's moments; the sum over
+                    // the four children by two more exchanges
+                    double Ssum[PL];
+                    double e2 = 0.0;
+#pragma unroll
+                    for (int i = 0; i < PL; ++i) {
+                        double v = acc[i] + __shfl_xor(acc[i], 16, 64);
+                        v += __shfl_xor(v, 32, 64);
+                        Ssum[i] = v;
+                        const double df = v - IT[i];
+                        e2 = __builtin_fma(df, df, e2);
+                    }
+                    // every row holds the same children sum: row 0's total decides
+                    const double err2 = lane0(row_sum16(e2));
+                    ++st_checks;
+                    st_visits += 4;
+                    const bool ok = err2 <= thr * thr;
+                    bool accept = ok && L + 1 >= a.min_depth;
+                    if (!accept && L + 1 >= a.max_depth) {
+                        accept = true;
+                        if (!ok) ++st_nonconv;
+                    }
+                    if (accept) {
+                        if (grp16 == 0) {
+                            double *dst = S::TOT_LDS ? s_tot + s * NV : a.val + C * s_off[s];
+#pragma unroll
+                            for (int i = 0; i < PL; ++i) {
+                                const int comp = PL * l16 + i;
+                                if (comp < NV) dst[comp] += Ssum[i];
+                            }
+                        }
+                        if ((unsigned long long)(L + 1) > st_maxlev) st_maxlev = L + 1;
+                    } else {
+                        double *dst = mptr(L + 1, grp16, s);
+#pragma unroll
+                        for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = acc[i];
+                        if (lane == 0) atomicOr(&s_fail, 1ull << s);
+                    }
                 }
             }
             __syncthreads();
