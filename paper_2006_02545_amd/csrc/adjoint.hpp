@@ -200,8 +200,9 @@ struct AdjArgs {
     const int64_t *pptr;      // first patch-major near pair of each patch
     double *gc_item;          // [chunks][6 ND_pad]: chart-coefficient gradient per work item
     double *t_pair;           // [pairs][12]: target gradient, dk, phiS, phiD per pair
-    double *gc_self;          // [N][6 ND_pad]: chart-coefficient gradient per self pair (by node)
-    int gc_pitch;             // 6 * ND_max
+    double *gc_self;          // [N][6 ND_max]: chart-coefficient gradient per self pair (by node)
+    int gc_pitch;             // item row: 6 + 18 ND_max (scalars, nine moment vectors)
+    int self_pitch;           // 6 ND_max
 };
 
 // sigma(y) = sum_a s_a K_a (complex)
@@ -217,23 +218,42 @@ __device__ __forceinline__ void sigma_at(const double *sc, const double *K, doub
     }
 }
 
-// 64-lane sum into every lane (two butterfly stages per value).
-__device__ __forceinline__ double wave_sum64(double v) { return wave_sum(v); }
+// Sum over the wavefront, into every lane (row sums by rotation, then the
+// four rows).
+__device__ __forceinline__ double wave_total(double v)
+{
+    v = row_sum16(v);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
 
+// Adjoint of the near quadrature, one work item (patch, <= 64 targets) per
+// workgroup.  The forward's subdivision walk is replayed with its own
+// arithmetic (same work split, same tests).  After the test of a group, the
+// targets that accepted its children are differentiated with one thread per
+// child node: the thread sums the weighted kernel derivatives gX, gn over
+// those targets, and the group adds to nine moment vectors per wavefront,
+//     M[gX_c], M[(X_v x gn)_c], M[(gn x X_u)_c],  M[f]_m = sum_q f(q) K_m(q),
+// each reduced over the wavefront's 64 nodes like the forward's moments.
+// The chart-coefficient gradient follows at the end from the differentiation
+// matrices of the basis:  dPhi/dchi_c = M[gX_c] + Du M[b_c] + Dv M[d_c].
 template <int D>
 __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
 {
     using S = PatchShape<D, true>;
-    constexpr int ND = S::ND, W = S::W, PL = S::PL, GS = S::GS, G0 = S::G0;
-    constexpr int NG = 6 * ND;  // real components of the chart-coefficient gradient
+    constexpr int ND = S::ND, W = S::W, PL = S::PL, G0 = S::G0, KS = S::KS, R = S::R;
+    constexpr int GSA = (KS + 7 + 6) | 1;   // forward row + X_u, X_v
     const PatchArgs &a = aa.pa;
-    __shared__ double s_geo[256 * GS];
+    __shared__ double s_geo[256 * GSA];
     __shared__ GroupEntry s_stack[kGroupStack];
     __shared__ double s_x[64][3];
     __shared__ double s_lam[64][2];
     __shared__ int32_t s_pair[64];
-    __shared__ double s_t[64][12];
-    __shared__ double s_gw[4][NG];
+    __shared__ double s_t[64][6];
+    __shared__ double s_tw[2][4][6];
+    __shared__ double s_sc[2 * KS];
+    __shared__ double s_cf[3 * ND];
     __shared__ double s_cm[4 * W];
     __shared__ unsigned long long s_fail;
     __shared__ int s_sp;
@@ -248,8 +268,10 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
     for (int64_t it = blockIdx.x; it < a.item_count; it += gridDim.x) {
         const int32_t *item = a.items + 3 * (a.item_seg + it);
         const int j = item[0], start = item[1], count = item[2];
-        const double *cf = a.coef + 3 * a.pb.node_ptr[j];
-        const double *sc = aa.scoef + 2 * a.pb.node_ptr[j];
+        const int64_t nb = a.pb.node_ptr[j];
+        for (int k = tid; k < 3 * ND; k += 256) s_cf[k] = a.coef[3 * nb + k];
+        for (int k = tid; k < 2 * KS; k += 256) s_sc[k] = k < 2 * ND ? aa.scoef[2 * nb + k] : 0.0;
+        const double *cf = s_cf;
         const double tau = a.tau[j];
         if (tid < count) {
             const int p = a.plist[start + tid];
@@ -261,12 +283,11 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
             s_lam[tid][1] = -aa.lam[2 * t + 1];  // conj(lambda)
             s_pair[tid] = p;
         }
-        for (int k = tid; k < 64 * 12; k += 256) (&s_t[0][0])[k] = 0.0;
-        for (int k = tid; k < 4 * NG; k += 256) (&s_gw[0][0])[k] = 0.0;
+        for (int k = tid; k < 64 * 6; k += 256) (&s_t[0][0])[k] = 0.0;
         if (tid < 64)
-            node_geometry<D, true>(cf, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, a.rule[3 * tid],
-                                   a.rule[3 * tid + 1], a.rule[3 * tid + 2], s_geo + tid * GS,
-                                   tid & 15);
+            node_geometry<D, true, true>(cf, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, a.rule[3 * tid],
+                                         a.rule[3 * tid + 1], a.rule[3 * tid + 2],
+                                         s_geo + tid * GSA, tid & 15);
         __syncthreads();
         // root moments (as in the forward)
         for (int s = wv; s < count; s += 4) {
@@ -274,7 +295,7 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
             double acc[W];
 #pragma unroll
             for (int v = 0; v < W; ++v) acc[v] = 0.0;
-            const double *g = s_geo + lane * GS;
+            const double *g = s_geo + lane * GSA;
             double fr, fi;
             kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
             mac_node<D, true>(acc, g, fr, fi);
@@ -299,11 +320,11 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
             s_sp = 1;
         }
         __syncthreads();
-        // per-wave chart-coefficient gradient, accumulated in registers over
-        // every accepted check this wave handles
-        double GC[NG];
+        // per-wavefront moment vectors (unit l16 of each) and scalar sums
+        double GM[9 * PL];
 #pragma unroll
-        for (int v = 0; v < NG; ++v) GC[v] = 0.0;
+        for (int v = 0; v < 9 * PL; ++v) GM[v] = 0.0;
+        double SC[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // dPhi/dk, Phi_S, Phi_D
         while (true) {
             if (s_sp == 0) break;
             const GroupEntry e = s_stack[s_sp - 1];
@@ -325,53 +346,17 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                 else if (c == 1) { Ax = abx; Ay = aby; Bx = bx; By = by; Cx = bcx; Cy = bcy; }
                 else if (c == 2) { Ax = cax; Ay = cay; Bx = bcx; By = bcy; Cx = cx; Cy = cy; }
                 else { Ax = bcx; Ay = bcy; Bx = cax; By = cay; Cx = abx; Cy = aby; }
-                node_geometry<D, true>(cf, Ax, Ay, Bx, By, Cx, Cy, a.rule[3 * q], a.rule[3 * q + 1],
-                                       a.rule[3 * q + 2] * area, s_geo + tid * GS, tid & 15);
+                node_geometry<D, true, true>(cf, Ax, Ay, Bx, By, Cx, Cy, a.rule[3 * q],
+                                             a.rule[3 * q + 1], a.rule[3 * q + 2] * area,
+                                             s_geo + tid * GSA, tid & 15);
             }
             __syncthreads();
             const double thr = tau * __builtin_ldexp(1.0, -2 * e.level);
             const int L = e.level;
-            // this lane's child triangle, for the gradient pass
-            double Ax, Ay, Bx, By, Cx, Cy;
-            if (grp16 == 0) { Ax = ax; Ay = ay; Bx = abx; By = aby; Cx = cax; Cy = cay; }
-            else if (grp16 == 1) { Ax = abx; Ay = aby; Bx = bx; By = by; Cx = bcx; Cy = bcy; }
-            else if (grp16 == 2) { Ax = cax; Ay = cay; Bx = bcx; By = bcy; Cx = cx; Cy = cy; }
-            else { Ax = bcx; Ay = bcy; Bx = cax; By = cay; Cx = abx; Cy = aby; }
-            // gradient pass for target s over the 256 children nodes, 4 per lane
-            auto grad_pass = [&](int s, const double *x) {
-                const double lr = s_lam[s][0], li = s_lam[s][1];
-                double T12[12];
-#pragma unroll
-                for (int v = 0; v < 12; ++v) T12[v] = 0.0;
-#pragma unroll 1
-                for (int i = 0; i < 4; ++i) {
-                    const int q = l16 + 16 * i;
-                    const double ru = a.rule[3 * q], rv = a.rule[3 * q + 1];
-                    const double wq = a.rule[3 * q + 2] * area;
-                    const double u = Ax + ru * (Bx - Ax) + rv * (Cx - Ax);
-                    const double v = Ay + ru * (By - Ay) + rv * (Cy - Ay);
-                    double K[ND], Ku[ND], Kv[ND], X[3], Xu[3], Xv[3];
-                    chart_eval_d<D>(cf, u, v, K, Ku, Kv, X, Xu, Xv);
-                    const double n[3] = {Xu[1] * Xv[2] - Xu[2] * Xv[1], Xu[2] * Xv[0] - Xu[0] * Xv[2],
-                                         Xu[0] * Xv[1] - Xu[1] * Xv[0]};
-                    double sgr, sgi, rhr, rhi;
-                    sigma_at<ND>(sc, K, sgr, sgi);
-                    cmul(lr, li, sgr, sgi, rhr, rhi);
-                    NodeGrad gg;
-                    node_grad(a.kern, x, X, n, wq, rhr, rhi, gg);
-                    accumulate_node<ND>(gg, K, Ku, Kv, Xu, Xv, GC, T12);
-                }
-#pragma unroll
-                for (int v = 0; v < 12; ++v) {
-                    const double tv = wave_sum(T12[v]);
-                    if (lane == 0) s_t[s][v] += tv;
-                }
-            };
-            // the forward's work split and test, in the same arithmetic
+            // ---- the forward's work split and test, in the same arithmetic
             const int kofs = (int)((ngroup++ + blockIdx.x) & 3);
             if (__builtin_popcountll(e.mask) == 1) {
                 const int s = __builtin_ctzll(e.mask);
-                const bool mine = wv == kofs;
                 const double x[3] = {s_x[s][0], s_x[s][1], s_x[s][2]};
                 double IT[PL];
                 {
@@ -383,7 +368,7 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
 #pragma unroll
                 for (int v = 0; v < W; ++v) acc[v] = 0.0;
                 {
-                    const double *g = s_geo + tid * GS;
+                    const double *g = s_geo + tid * GSA;
                     double fr, fi;
                     kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
                     mac_node<D, true>(acc, g, fr, fi);
@@ -409,17 +394,15 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                 const double err2 = lane0(row_sum16(e2));
                 bool accept = err2 <= thr * thr && L + 1 >= a.min_depth;
                 if (!accept && L + 1 >= a.max_depth) accept = true;
-                if (accept) {
-                    if (mine) grad_pass(s, x);
-                } else {
-                        if (grp16 == 0) {
-                            double *dst = mptr(L + 1, wv, s);
+                if (!accept) {
+                    if (grp16 == 0) {
+                        double *dst = mptr(L + 1, wv, s);
 #pragma unroll
-                            for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = cm[i];
-                        }
-                        if (tid == 0) s_fail = 1ull << s;
+                        for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = cm[i];
                     }
-                } else {
+                    if (tid == 0) s_fail = 1ull << s;
+                }
+            } else {
                 unsigned long long mk = e.mask;
                 int k = kofs;
                 while (mk) {
@@ -438,13 +421,12 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                     for (int v = 0; v < W; ++v) acc[v] = 0.0;
 #pragma unroll 1
                     for (int i = 0; i < 4; ++i) {
-                        const double *g = s_geo + (grp16 * 64 + l16 + 16 * i) * GS;
+                        const double *g = s_geo + (grp16 * 64 + l16 + 16 * i) * GSA;
                         double fr, fi;
                         kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
                         mac_node<D, true>(acc, g, fr, fi);
                     }
                     rot_reduce16<PL>(acc);
-                    // the forward's test, in the same arithmetic
                     double e2 = 0.0;
 #pragma unroll
                     for (int i = 0; i < PL; ++i) {
@@ -456,13 +438,95 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                     const double err2 = lane0(row_sum16(e2));
                     bool accept = err2 <= thr * thr && L + 1 >= a.min_depth;
                     if (!accept && L + 1 >= a.max_depth) accept = true;
-                    if (accept) {
-                        grad_pass(s, x);
-                    } else {
+                    if (!accept) {
                         double *dst = mptr(L + 1, grp16, s);
 #pragma unroll
                         for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = acc[i];
                         if (lane == 0) atomicOr(&s_fail, 1ull << s);
+                    }
+                }
+            }
+            __syncthreads();
+            // ---- gradient over the children nodes for the accepting targets
+            const unsigned long long accm = e.mask & ~s_fail;
+            if (accm != 0ull) {
+                const double *g = s_geo + tid * GSA;
+                const double X[3] = {g[G0], g[G0 + 1], g[G0 + 2]};
+                const double Xu[3] = {g[G0 + 7], g[G0 + 8], g[G0 + 9]};
+                const double Xv[3] = {g[G0 + 10], g[G0 + 11], g[G0 + 12]};
+                const double n[3] = {Xu[1] * Xv[2] - Xu[2] * Xv[1], Xu[2] * Xv[0] - Xu[0] * Xv[2],
+                                     Xu[0] * Xv[1] - Xu[1] * Xv[0]};
+                const double wq = a.rule[3 * (tid & 63) + 2] * area;
+                // sigma(y) from the rotated basis slots
+                double sgr = 0.0, sgi = 0.0;
+#pragma unroll
+                for (int p = 0; p < 16; ++p)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int m = ((l16 + p) & 15) * R + r;
+                        const double kv = g[p * R + r];
+                        sgr = __builtin_fma(s_sc[2 * m], kv, sgr);
+                        sgi = __builtin_fma(s_sc[2 * m + 1], kv, sgi);
+                    }
+                double gX[6] = {0, 0, 0, 0, 0, 0}, gn[6] = {0, 0, 0, 0, 0, 0};
+                unsigned long long mk = accm;
+                int buf = 0;
+                while (mk) {
+                    const int s = __builtin_ctzll(mk);
+                    mk &= mk - 1ull;
+                    const double x[3] = {s_x[s][0], s_x[s][1], s_x[s][2]};
+                    double rhr, rhi;
+                    cmul(s_lam[s][0], s_lam[s][1], sgr, sgi, rhr, rhi);
+                    NodeGrad gg;
+                    node_grad(a.kern, x, X, n, wq, rhr, rhi, gg);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        gX[2 * c] += gg.gXr[c];
+                        gX[2 * c + 1] += gg.gXi[c];
+                        gn[2 * c] += gg.gnr[c];
+                        gn[2 * c + 1] += gg.gni[c];
+                    }
+                    SC[0] += gg.gkr; SC[1] += gg.gki;
+                    SC[2] += gg.sr; SC[3] += gg.si;
+                    SC[4] += gg.dr; SC[5] += gg.di;
+                    // target gradient: -sum of gX over the 256 nodes
+#pragma unroll
+                    for (int v = 0; v < 6; ++v) {
+                        const double tv = wave_total(v & 1 ? gg.gXi[v >> 1] : gg.gXr[v >> 1]);
+                        if (lane == 0) s_tw[buf][wv][v] = tv;
+                    }
+                    __syncthreads();
+                    if (tid < 6)
+                        s_t[s][tid] -= (s_tw[buf][0][tid] + s_tw[buf][1][tid]) +
+                                       (s_tw[buf][2][tid] + s_tw[buf][3][tid]);
+                    buf ^= 1;
+                }
+                // nine moment vectors of this wavefront's 64 nodes
+                double bv[6], dv[6];
+#pragma unroll
+                for (int ri = 0; ri < 2; ++ri) {
+                    const double g0 = gn[ri], g1 = gn[2 + ri], g2 = gn[4 + ri];
+                    bv[ri] = Xv[1] * g2 - Xv[2] * g1;
+                    bv[2 + ri] = Xv[2] * g0 - Xv[0] * g2;
+                    bv[4 + ri] = Xv[0] * g1 - Xv[1] * g0;
+                    dv[ri] = g1 * Xu[2] - g2 * Xu[1];
+                    dv[2 + ri] = g2 * Xu[0] - g0 * Xu[2];
+                    dv[4 + ri] = g0 * Xu[1] - g1 * Xu[0];
+                }
+#pragma unroll
+                for (int v = 0; v < 9; ++v) {
+                    const double *f = v < 3 ? gX : (v < 6 ? bv : dv);
+                    const int c = v % 3;
+                    double acc[W];
+#pragma unroll
+                    for (int i = 0; i < W; ++i) acc[i] = 0.0;
+                    mac_node<D, true>(acc, g, f[2 * c], f[2 * c + 1]);
+                    rot_reduce16<PL>(acc);
+#pragma unroll
+                    for (int i = 0; i < PL; ++i) {
+                        double t = acc[i] + __shfl_xor(acc[i], 16, 64);
+                        t += __shfl_xor(t, 32, 64);
+                        GM[v * PL + i] += t;
                     }
                 }
             }
@@ -485,20 +549,38 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
             }
             __syncthreads();
         }
-        // per-wave coefficient gradient: lane sums in fixed order, then the
-        // four waves in order
+        // per-wavefront parts to LDS (over the geometry rows, free here), then
+        // the four in order
+        double (*s_gw)[9 * PL * 16 + 6] = reinterpret_cast<double (*)[9 * PL * 16 + 6]>(s_geo);
+        static_assert(4 * (9 * PL * 16 + 6) <= 256 * GSA, "reduction buffer exceeds the geometry rows");
+        if (grp16 == 0) {
 #pragma unroll
-        for (int v = 0; v < NG; ++v) {
-            const double tv = wave_sum(GC[v]);
-            if (lane == 0) s_gw[wv][v] = tv;
+            for (int v = 0; v < 9; ++v)
+#pragma unroll
+                for (int i = 0; i < PL; ++i) s_gw[wv][v * PL * 16 + PL * l16 + i] = GM[v * PL + i];
+        }
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+            const double tv = wave_total(SC[v]);
+            if (lane == 0) s_gw[wv][9 * PL * 16 + v] = tv;
         }
         __syncthreads();
         {
             const int64_t chunk = aa.cptr[j] + (start - aa.pptr[j]) / 64;
             double *dst = aa.gc_item + chunk * aa.gc_pitch;
-            for (int v = tid; v < NG; v += 256) dst[v] = s_gw[0][v] + s_gw[1][v] + s_gw[2][v] + s_gw[3][v];
-            for (int k2 = tid; k2 < count * 12; k2 += 256) {
-                const int s = k2 / 12, v = k2 - s * 12;
+            // row: 6 scalars (dPhi/dk, Phi_S, Phi_D), then the moment vectors
+            // dst[6 + v * 2 ND + comp], comp < 2 ND
+            if (tid < 6) {
+                const int o = 9 * PL * 16 + tid;
+                dst[tid] = (s_gw[0][o] + s_gw[1][o]) + (s_gw[2][o] + s_gw[3][o]);
+            }
+            for (int k2 = tid; k2 < 9 * 2 * ND; k2 += 256) {
+                const int v = k2 / (2 * ND), comp = k2 - v * 2 * ND;
+                const int o = v * PL * 16 + comp;
+                dst[6 + k2] = (s_gw[0][o] + s_gw[1][o]) + (s_gw[2][o] + s_gw[3][o]);
+            }
+            for (int k2 = tid; k2 < count * 6; k2 += 256) {
+                const int s = k2 / 6, v = k2 - s * 6;
                 aa.t_pair[(int64_t)s_pair[s] * 12 + v] = s_t[s][v];
             }
         }
@@ -599,7 +681,7 @@ __global__ __launch_bounds__(64) void k_adjoint_self(AdjArgs aa)
             node_grad(a.kern, x, X, n, s * det * ws * dlam, rhr, rhi, gg);
             accumulate_node<ND>(gg, K, Ku, Kv, Xu, Xv, GC, T12);
         }
-        double *dst = aa.gc_self + node * aa.gc_pitch;
+        double *dst = aa.gc_self + node * aa.self_pitch;
 #pragma unroll
         for (int v = 0; v < NG; ++v) {
             const double tv2 = wave_sum(GC[v]);
@@ -638,25 +720,40 @@ __global__ void k_sigma_coef(Problem pb, DegTab tab, const double *sigma, double
 // work-item parts (chunk order) and the self parts (node order), then
 // grad_l,c = sum_a V_(a),l G_c,a.
 __global__ void k_adj_patch_final(Problem pb, DegTab tab, const int64_t *cptr,
-                                  const int64_t *nchunk, const double *gc_item,
-                                  const double *gc_self, const unsigned int *is_self_node,
-                                  int pitch, double *grad)
+                                  const int64_t *nchunk, const double *gc_item, int item_pitch,
+                                  const double *gc_self, int self_pitch,
+                                  const unsigned int *is_self_node, double *grad)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= pb.P) return;
     const int d = pb.degree[j];
     const int nd = nd_of(d);
     const double *V = tab.V[d];
+    const double *Du = tab.D[d], *Dv = tab.D[d] + nd * nd;
     const int64_t nb = pb.node_ptr[j];
     double G[6 * kNDMax];
     for (int v = 0; v < 6 * nd; ++v) G[v] = 0.0;
+    // work items in chunk order: dPhi/dchi_c = M[gX_c] + Du M[b_c] + Dv M[d_c]
     for (int64_t c = 0; c < nchunk[j]; ++c) {
-        const double *src = gc_item + (cptr[j] + c) * pitch;
-        for (int v = 0; v < 6 * nd; ++v) G[v] += src[v];
+        const double *M = gc_item + (cptr[j] + c) * item_pitch + 6;
+        for (int cc = 0; cc < 3; ++cc)
+            for (int a = 0; a < nd; ++a) {
+                const double *Mx = M + cc * 2 * nd, *Mb = M + (3 + cc) * 2 * nd;
+                const double *Md = M + (6 + cc) * 2 * nd;
+                double gr = Mx[2 * a], gi = Mx[2 * a + 1];
+                for (int m = 0; m < nd; ++m) {
+                    gr = __builtin_fma(Du[a * nd + m], Mb[2 * m], gr);
+                    gi = __builtin_fma(Du[a * nd + m], Mb[2 * m + 1], gi);
+                    gr = __builtin_fma(Dv[a * nd + m], Md[2 * m], gr);
+                    gi = __builtin_fma(Dv[a * nd + m], Md[2 * m + 1], gi);
+                }
+                G[2 * (cc * nd + a)] += gr;
+                G[2 * (cc * nd + a) + 1] += gi;
+            }
     }
     for (int l = 0; l < nd; ++l) {
         if (!is_self_node[nb + l]) continue;
-        const double *src = gc_self + (nb + l) * pitch;
+        const double *src = gc_self + (nb + l) * self_pitch;
         for (int v = 0; v < 6 * nd; ++v) G[v] += src[v];
     }
     for (int l = 0; l < nd; ++l)
@@ -689,12 +786,16 @@ __global__ void k_adj_target_final(Problem pb, const int64_t *pair_ptr, const do
 // dPhi/dk, dPhi/dalpha = Phi_S, dPhi/dbeta = Phi_D: fixed-order block sum
 // over the pairs.
 __global__ __launch_bounds__(256) void k_adj_scalars(int64_t np, const double *t_pair,
-                                                     double *grad_k, double *dphi)
+                                                     int64_t nitems, const double *gc_item,
+                                                     int item_pitch, double *grad_k, double *dphi)
 {
     __shared__ double s[256][6];
     double acc[6] = {0, 0, 0, 0, 0, 0};
+    // self pairs carry theirs per pair, near work items per item
     for (int64_t p = threadIdx.x; p < np; p += 256)
         for (int v = 0; v < 6; ++v) acc[v] += t_pair[p * 12 + 6 + v];
+    for (int64_t c = threadIdx.x; c < nitems; c += 256)
+        for (int v = 0; v < 6; ++v) acc[v] += gc_item[c * item_pitch + v];
     for (int v = 0; v < 6; ++v) s[threadIdx.x][v] = acc[v];
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {

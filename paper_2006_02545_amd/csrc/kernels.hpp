@@ -44,6 +44,7 @@ struct DegTab {
     const double *V[9];   // [nd][nd] per degree, V[a * nd + l]
     const double *uv[9];  // [nd][2]
     const double *w[9];   // [nd]
+    const double *D[9];   // [2][nd][nd] differentiation matrices in the basis
     double normV[9];
     int present[9];
 };

@@ -124,7 +124,7 @@ __device__ __forceinline__ double lane0(double v)
 // Geometry of one rule node of triangle (A, B, C) into LDS row g: basis
 // values in the rotated slot order of reader row lane l16 (padding slots 0),
 // then y, n w, J w.
-template <int D, bool CPLX>
+template <int D, bool CPLX, bool DERIV = false>
 __device__ __forceinline__ void node_geometry(const double *cf, double Ax, double Ay, double Bx,
                                               double By, double Cx, double Cy, double ru, double rv,
                                               double wgt, double *g, int l16)
@@ -142,6 +142,11 @@ __device__ __forceinline__ void node_geometry(const double *cf, double Ax, doubl
     g[G0 + 0] = X[0]; g[G0 + 1] = X[1]; g[G0 + 2] = X[2];
     g[G0 + 3] = n0 * wgt; g[G0 + 4] = n1 * wgt; g[G0 + 5] = n2 * wgt;
     g[G0 + 6] = __builtin_sqrt(n0 * n0 + n1 * n1 + n2 * n2) * wgt;
+    if (DERIV) {
+        // chart derivatives for the adjoint
+        g[G0 + 7] = Xu[0]; g[G0 + 8] = Xu[1]; g[G0 + 9] = Xu[2];
+        g[G0 + 10] = Xv[0]; g[G0 + 11] = Xv[1]; g[G0 + 12] = Xv[2];
+    }
     int rot = (16 - l16) & 15;
     // keep the slot addresses local to this call (hoisting them out of the
     // caller's loops would pin 16 R registers for the whole kernel)

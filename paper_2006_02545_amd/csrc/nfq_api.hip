@@ -20,7 +20,7 @@ struct nfq_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     RefData ref[9];
-    double *dV[9] = {}, *duv[9] = {}, *dw[9] = {};
+    double *dV[9] = {}, *duv[9] = {}, *dw[9] = {}, *dD[9] = {};
     double *drule = nullptr;         // [64][3]
     double *dglr = nullptr, *dgla = nullptr;
     int nr = 0, na = 0;
@@ -228,6 +228,7 @@ DegTab make_tab(const nfq_ctx *ctx)
         t.V[d] = ctx->dV[d];
         t.uv[d] = ctx->duv[d];
         t.w[d] = ctx->dw[d];
+        t.D[d] = ctx->dD[d];
         t.normV[d] = ctx->ref[d].normV;
         t.present[d] = ctx->dV[d] != nullptr;
     }
@@ -475,6 +476,7 @@ void nfq_destroy(nfq_ctx *ctx)
         if (ctx->dV[d]) (void)hipFree(ctx->dV[d]);
         if (ctx->duv[d]) (void)hipFree(ctx->duv[d]);
         if (ctx->dw[d]) (void)hipFree(ctx->dw[d]);
+        if (ctx->dD[d]) (void)hipFree(ctx->dD[d]);
     }
     if (ctx->drule) (void)hipFree(ctx->drule);
     if (ctx->dglr) (void)hipFree(ctx->dglr);
@@ -490,14 +492,19 @@ nfq_status nfq_register_degree(nfq_ctx *ctx, int d, const double *ref_uv, const 
     std::string msg = build_reference(d, ref_uv, ref_w, r);
     if (!msg.empty()) return fail(ctx, NFQ_ERR_INVALID_ARG, msg);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    if (ctx->dV[d]) { (void)hipFree(ctx->dV[d]); (void)hipFree(ctx->duv[d]); (void)hipFree(ctx->dw[d]); }
-    ctx->dV[d] = ctx->duv[d] = ctx->dw[d] = nullptr;
+    if (ctx->dV[d]) {
+        (void)hipFree(ctx->dV[d]); (void)hipFree(ctx->duv[d]); (void)hipFree(ctx->dw[d]);
+        (void)hipFree(ctx->dD[d]);
+    }
+    ctx->dV[d] = ctx->duv[d] = ctx->dw[d] = ctx->dD[d] = nullptr;
     HIP_TRY(ctx, dalloc(&ctx->dV[d], r.V.size()));
     HIP_TRY(ctx, dalloc(&ctx->duv[d], r.uv.size()));
     HIP_TRY(ctx, dalloc(&ctx->dw[d], r.w.size()));
+    HIP_TRY(ctx, dalloc(&ctx->dD[d], r.D.size()));
     HIP_TRY(ctx, hipMemcpy(ctx->dV[d], r.V.data(), r.V.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(ctx->duv[d], r.uv.data(), r.uv.size() * 8, hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(ctx->dw[d], r.w.data(), r.w.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(ctx->dD[d], r.D.data(), r.D.size() * 8, hipMemcpyHostToDevice));
     ctx->ref[d] = r;
     return NFQ_OK;
 }
@@ -790,7 +797,8 @@ nfq_status nfq_adjoint(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *p
     const Problem &pb = pl->pb;
     const int64_t N = pb.N, NT = pb.NT;
     // adjoint scratch (allocated on first use)
-    const int pitch = 6 * nd_of(pl->max_degree > 0 ? pl->max_degree : 1);
+    const int ndmax = nd_of(pl->max_degree > 0 ? pl->max_degree : 1);
+    const int pitch = 6 + 18 * ndmax, self_pitch = 6 * ndmax;
     if (!pl->scoef || pl->gc_pitch < pitch) {
         (void)hipFree(pl->scoef); (void)hipFree(pl->gc_item); (void)hipFree(pl->t_pair);
         (void)hipFree(pl->gc_self); (void)hipFree(pl->self_mark);
@@ -799,7 +807,7 @@ nfq_status nfq_adjoint(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *p
         HIP_TRY(ctx, dalloc(&pl->scoef, 2 * N));
         HIP_TRY(ctx, dalloc(&pl->gc_item, std::max<int64_t>(pl->n_items, 1) * pitch));
         HIP_TRY(ctx, dalloc(&pl->t_pair, std::max<int64_t>(pl->npairs, 1) * 12));
-        HIP_TRY(ctx, dalloc(&pl->gc_self, N * pitch));
+        HIP_TRY(ctx, dalloc(&pl->gc_self, N * self_pitch));
         HIP_TRY(ctx, dalloc(&pl->self_mark, N));
         pl->gc_pitch = pitch;
     }
@@ -827,6 +835,7 @@ nfq_status nfq_adjoint(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *p
     aa.t_pair = pl->t_pair;
     aa.gc_self = pl->gc_self;
     aa.gc_pitch = pitch;
+    aa.self_pitch = self_pitch;
     for (int d = 1; d <= 8; ++d) {
         const int64_t ss = pl->seg_start_h[9 + d], sc = pl->seg_len_h[9 + d];
         AdjArgs ad = aa;
@@ -858,12 +867,13 @@ nfq_status nfq_adjoint(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *p
         }
     }
     hipLaunchKernelGGL(k_adj_patch_final, dim3(nblk(pb.P, 64)), dim3(64), 0, st, pb, tab, pl->cptr,
-                       pl->nchunk, pl->gc_item, pl->gc_self, pl->self_mark, pitch, (double *)grad_xyz);
+                       pl->nchunk, pl->gc_item, pitch, pl->gc_self, self_pitch, pl->self_mark,
+                       (double *)grad_xyz);
     if (NT > 0)
         hipLaunchKernelGGL(k_adj_target_final, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, pl->pair_ptr,
                            pl->t_pair, (double *)grad_xyz);
     hipLaunchKernelGGL(k_adj_scalars, dim3(1), dim3(256), 0, st, pl->npairs, pl->t_pair,
-                       (double *)grad_k, (double *)dphi_dab);
+                       pl->n_items, pl->gc_item, pitch, (double *)grad_k, (double *)dphi_dab);
     HIP_TRY(ctx, hipGetLastError());
     int hflags[kNumFlags];
     HIP_TRY(ctx, hipMemcpyAsync(hflags, pl->flags, sizeof(hflags), hipMemcpyDeviceToHost, st));

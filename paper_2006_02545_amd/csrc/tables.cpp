@@ -219,6 +219,30 @@ std::string build_reference(int d, const double *uv, const double *w_in, RefData
     out.w.resize(nd);
     for (int l = 0; l < nd; ++l)
         out.w[l] = w_in ? w_in[l] : out.V[0 * nd + l] / std::sqrt(2.0);
+    // differentiation matrices by projection; the conical rule with d + 2
+    // points is exact for the degree 2d - 1 products
+    std::vector<double> rule;
+    conical_rule(d + 2, rule);
+    std::vector<long double> Du(nd * nd, 0.0L), Dv(nd * nd, 0.0L);
+    std::vector<double> K(nd), Ku(nd), Kv(nd);
+    for (size_t q = 0; q < rule.size() / 3; ++q) {
+        koorn_visit_rt(d, rule[3 * q], rule[3 * q + 1], [&](int a, double k, double ku, double kv) {
+            K[a] = k;
+            Ku[a] = ku;
+            Kv[a] = kv;
+        });
+        const long double w = rule[3 * q + 2];
+        for (int a = 0; a < nd; ++a)
+            for (int m = 0; m < nd; ++m) {
+                Du[a * nd + m] += w * Ku[a] * K[m];
+                Dv[a * nd + m] += w * Kv[a] * K[m];
+            }
+    }
+    out.D.resize(2 * nd * nd);
+    for (int i = 0; i < nd * nd; ++i) {
+        out.D[i] = (double)Du[i];
+        out.D[nd * nd + i] = (double)Dv[i];
+    }
     return "";
 }
 

@@ -12,6 +12,8 @@ struct RefData {
     std::vector<double> uv;   // [nd][2] interpolation nodes on T0
     std::vector<double> V;    // [nd][nd], V[a * nd + l]: values -> Koornwinder coefficients
     std::vector<double> w;    // [nd] quadrature weights at the nodes
+    std::vector<double> D;    // [2][nd][nd]: D[0][a][m] = int_T0 dK_a/du K_m, D[1]: d/dv
+                              // (K orthonormal on T0, so dK_a/du = sum_m D[0][a][m] K_m)
     double normV = 0.0;       // ||V||_2
     double cond = 0.0;        // ||U||_2 ||V||_2
 };
