@@ -37,14 +37,17 @@ def kernel_flops(prob):
     return C_KERNEL["laplace"] if prob.real_kernel else C_KERNEL["laplace_cplx"]
 
 
-def cpu_baseline(prob, seconds):
-    """The oracle (method mode, one thread) on whole rows of randomly chosen
-    targets of the same workload, until `seconds` of CPU work are spent."""
+def _oracle_rows(args):
+    """Worker: whole rows (near + self blocks) of randomly chosen targets of the
+    workload, oracle method mode, until `seconds` are spent.  Returns the
+    number of rows done and the seconds taken."""
+    seed, seconds = args
     import numpy as np
     import oracle
+    from paper_2006_02545_amd import surfaces
+    prob = surfaces.config(1)
     run = oracle.OracleRun(prob, mode=oracle.METHOD)
-    rng = np.random.default_rng(2024)
-    order = rng.permutation(prob.NT)
+    order = np.random.default_rng(seed).permutation(prob.NT)
     done = 0
     t0 = time.perf_counter()
     for t in order:
@@ -54,10 +57,54 @@ def cpu_baseline(prob, seconds):
         done += 1
         if time.perf_counter() - t0 >= seconds:
             break
-    el = time.perf_counter() - t0
-    return {"value": done / el, "unit": "target-points/s", "cores": 1, "kind": "oracle",
-            "sample": "%d random targets of the same workload, full rows (near + self blocks), "
-                      "oracle method mode, one thread, %.1f s" % (done, el)}
+    return done, time.perf_counter() - t0
+
+
+def cpu_baseline(seconds, workers):
+    """The oracle on the host: `workers` processes (one thread each), each on
+    its own random sample of target rows for about `seconds`."""
+    import multiprocessing as mp
+    if workers <= 1:
+        done, el = _oracle_rows((2024, seconds))
+        rate = done / el
+    else:
+        with mp.get_context("spawn").Pool(workers) as pool:
+            res = pool.map(_oracle_rows, [(2024 + i, seconds) for i in range(workers)])
+        done = sum(r[0] for r in res)
+        rate = sum(r[0] / r[1] for r in res)
+        el = max(r[1] for r in res)
+    return {"value": rate, "unit": "target-points/s", "cores": workers, "kind": "oracle",
+            "sample": "%d random target rows of the same workload (near + self blocks), oracle "
+                      "method mode, %d process(es) x 1 thread, %.1f s each" % (done, workers, el)}
+
+
+# HBM traffic of the near kernel per launch on this workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), scaled
+# by the same counters on a plain 1 GiB copy kernel (bench.py
+# --copy-calibration 1024: FETCH_SIZE reads 0.5 GiB, WRITE_SIZE 1 GiB), valid
+# for the kernel sources with this digest.
+TRAFFIC_RECORD = {
+    "sources_sha256": "e2d36be77cfc103cdcdd5fb37dbada58a689199bde208aacafbd777831b1c51e",
+    "fetch_kib": 158518.9, "write_kib": 361208.3,
+    "fetch_scale": 2.0, "write_scale": 1.0,
+}
+NEAR_SOURCES = ["near_patch.hpp", "kernels.hpp", "device.hpp", "fastmath.hpp", "koorn.hpp"]
+
+
+def near_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in NEAR_SOURCES:
+        with open(os.path.join(ROOT, "paper_2006_02545_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def near_traffic():
+    if TRAFFIC_RECORD["sources_sha256"] != near_sources_digest():
+        return None
+    r = TRAFFIC_RECORD
+    return (r["fetch_kib"] * r["fetch_scale"] + r["write_kib"] * r["write_scale"]) * 1024.0
 
 
 def main():
@@ -66,11 +113,18 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle processes for cpu_baseline (default: min(16, cpu count))")
+    ap.add_argument("--print-digest", action="store_true",
+                    help="print the digest of the near-kernel sources and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.print_digest:
+        print(near_sources_digest())
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration << 20
@@ -131,6 +185,18 @@ def main():
     torch.cuda.synchronize()
     ms_fa = (time.perf_counter() - t0) / nfa * 1e3
 
+    # the plain per-pair GPU path (one wavefront per pair, no reuse of
+    # subtriangle geometry across targets) on the same workload
+    for _ in range(2):
+        plan.generate(stats=False, per_pair=True, **gen)
+    torch.cuda.synchronize()
+    npp = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(npp):
+        plan.generate(stats=False, per_pair=True, **gen)
+    torch.cuda.synchronize()
+    ms_pp = (time.perf_counter() - t0) / npp * 1e3
+
     # per-phase durations from HIP events recorded on the library's stream
     phases = {k: 0.0 for k in ("ms_builder", "ms_prep", "ms_self", "ms_near", "ms_weights")}
     st = None
@@ -148,7 +214,7 @@ def main():
     achieved = flops_near / (phases["ms_near"] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": "k_near (adaptive near quadrature)",
                 "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": near_traffic(),
                 "flops_per_launch": flops_near, "ms_per_launch": phases["ms_near"]}
     out = {
         "metric": METRIC,
@@ -170,13 +236,16 @@ def main():
         "fwd_adjoint": {"value": prob.NT / (ms_fa * 1e-3), "unit": "target-points/s",
                         "ms_per_step": ms_fa, "steps": nfa,
                         "step": "generate + apply + adjoint (gradient wrt nodes, k, alpha, beta)"},
+        "per_pair_path": {"value": prob.NT / (ms_pp * 1e-3), "unit": "target-points/s",
+                          "ms_per_step": ms_pp, "steps": npp},
         "phase_ms": phases,
         "gen_stats": {k: st[k] for k in ("near_pairs", "self_pairs", "visits", "checks",
                                          "nonconverged", "max_level")},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+        workers = args.cpu_workers or max(1, min(16, os.cpu_count() or 1))
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, workers)
     print(json.dumps(out))
 
 
