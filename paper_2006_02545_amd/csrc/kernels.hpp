@@ -713,46 +713,68 @@ __global__ __launch_bounds__((64 * SelfShape<D, CPLX>::WPB)) void k_self(QuadArg
 
 // ------------------------------------------- moments -> node weights
 
-// In place on the output blocks of a (degree, kind) segment: for each pair,
-// a_l = sum_nm V_(nm),l I_nm (Section 4.3).  16 pairs per block.
+typedef double v4f64 __attribute__((ext_vector_type(4)));
+
+template <int D, bool CPLX>
+struct WeightsShape {
+    static constexpr int ND = nd_of(D);
+    static constexpr int C = CPLX ? 2 : 1;
+    static constexpr int PPT = 16 / C;          // pairs per 16-row tile
+    static constexpr int KS = (ND + 3) / 4;     // k steps of the 16x16x4 product
+    static constexpr int NTL = (ND + 15) / 16;  // 16-column tiles
+};
+
+// Moments -> node weights, in place on the output blocks of a (degree, kind)
+// segment: a_l = sum_nm V_(nm),l I_nm (Section 4.3), as a batched product on
+// the FP64 matrix cores.  Rows are (pair, re/im), columns the node l, the
+// contraction runs over the basis index:  A[row][m] = I_m, B[m][l] = V_(m),l.
+// One wavefront per 16 rows (8 complex or 16 real pairs).  Operand layout of
+// the 16x16x4 f64 product: lane q holds A[q % 16][q / 16], B[q / 16][q % 16]
+// and D[q / 16 + 4 r][q % 16], r = 0..3.  Each wavefront reads all moments of
+// its pairs before it writes their weights.
 template <int D, bool CPLX>
 __global__ __launch_bounds__(256) void k_weights(const int32_t *grp, int64_t seg, int64_t count,
                                                  const int64_t *pair_off, const double *V,
                                                  double *val)
 {
-    constexpr int ND = nd_of(D);
-    constexpr int C = CPLX ? 2 : 1;
-    constexpr int TP = 16;
-    __shared__ double s_mom[TP][C * ND];
-    __shared__ double s_V[ND * ND];
-    __shared__ int64_t s_off[TP];
-    const int64_t tile = blockIdx.x;
-    if (threadIdx.x < TP) {
-        const int64_t i = tile * TP + threadIdx.x;
-        const int p = i < count ? grp[seg + i] : -1;
-        s_off[threadIdx.x] = p >= 0 ? pair_off[p] : -1;
-    }
-    for (int k = threadIdx.x; k < ND * ND; k += blockDim.x) s_V[k] = V[k];
-    __syncthreads();
-    for (int k = threadIdx.x; k < TP * C * ND; k += blockDim.x) {
-        const int i = k / (C * ND), r = k - i * (C * ND);
-        const int64_t off = s_off[i];
-        s_mom[i][r] = off >= 0 ? val[C * off + r] : 0.0;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < TP * ND; k += blockDim.x) {
-        const int i = k / ND, l = k - i * ND;
-        const int64_t off = s_off[i];
-        if (off < 0) continue;
-        double sr = 0.0, si = 0.0;
+    using S = WeightsShape<D, CPLX>;
+    constexpr int ND = S::ND, C = S::C, PPT = S::PPT, KS = S::KS, NTL = S::NTL;
+    const int lane = threadIdx.x & 63;
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t ntiles = (count + PPT - 1) / PPT;
+    if (tile >= ntiles) return;  // uniform over the wavefront
+    // the A row of this lane
+    const int ia = lane & 15;
+    const int64_t ipa = tile * PPT + ia / C;
+    const int pa = ipa < count ? grp[seg + ipa] : -1;
+    const int64_t offa = pa >= 0 ? pair_off[pa] : -1;
+    const int parta = ia % C;
+    v4f64 acc[NTL];
 #pragma unroll
-        for (int m = 0; m < ND; ++m) {
-            const double vv = s_V[m * ND + l];
-            sr = __builtin_fma(vv, s_mom[i][C * m], sr);
-            if (CPLX) si = __builtin_fma(vv, s_mom[i][C * m + 1], si);
+    for (int t = 0; t < NTL; ++t) acc[t] = v4f64{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int m = 4 * s + (lane >> 4);
+        const double av = (offa >= 0 && m < ND) ? val[C * (offa + m) + parta] : 0.0;
+#pragma unroll
+        for (int t = 0; t < NTL; ++t) {
+            const int l = 16 * t + (lane & 15);
+            const double bv = (m < ND && l < ND) ? V[m * ND + l] : 0.0;
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
         }
-        val[C * (off + l)] = sr;
-        if (CPLX) val[C * (off + l) + 1] = si;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = (lane >> 4) + 4 * r;
+        const int64_t ip = tile * PPT + i / C;
+        const int p = ip < count ? grp[seg + ip] : -1;
+        if (p < 0) continue;
+        const int64_t off = pair_off[p];
+#pragma unroll
+        for (int t = 0; t < NTL; ++t) {
+            const int l = 16 * t + (lane & 15);
+            if (l < ND) val[C * (off + l) + i % C] = acc[t][r];
+        }
     }
 }
 

@@ -280,7 +280,9 @@ void launch_quad(const nfq_plan *pl, QuadArgs qa, int64_t near_seg, int64_t near
     const int64_t tot = near_cnt + self_cnt;  // both padded to 16, contiguous
     if (tot > 0) {
         tm.begin(kPhWeights, D, st);
-        hipLaunchKernelGGL((k_weights<D, CPLX>), dim3(nblk(tot, 16)), dim3(256), 0, st, qa.grp,
+        using WS = WeightsShape<D, CPLX>;
+        const int64_t tiles = (tot + WS::PPT - 1) / WS::PPT;  // 16-row tiles, 4 per block
+        hipLaunchKernelGGL((k_weights<D, CPLX>), dim3(nblk(tiles, 4)), dim3(256), 0, st, qa.grp,
                            near_seg, tot, qa.pair_off, pl->ctx->dV[D], qa.val);
         tm.end(kPhWeights, D, st);
     }
