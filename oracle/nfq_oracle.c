@@ -28,7 +28,10 @@
  *    (scaled tolerance of Section 4.2, eq. for q_j, and Section 4.3).
  *    Subtriangle rule: conical product (Gauss-Jacobi(1,0) x Gauss-Legendre),
  *    n_g points per direction (8 by default), standing in for the unprinted
- *    q-th order Vioreanu-Rokhlin rule.
+ *    q-th order Vioreanu-Rokhlin rule.  A test whose difference is below
+ *    the estimated double-precision rounding level of the moments is also
+ *    accepted (near a target the scaled threshold of deep subtriangles can
+ *    fall below that level, and refining further cannot help).
  *  - TRUTH: the same integrals to ~1e-13 relative (20-point rules, tight
  *    tolerance, deep trees) for parity checks.
  *  Self patches (both modes): the target splits T0 into three triangles,
@@ -47,6 +50,11 @@
 #define IU _Complex_I
 
 typedef double complex cplx;
+
+/* safety factor of the rounding-floor acceptance of the adaptive test */
+#ifndef ORC_NOISE_KAPPA
+#define ORC_NOISE_KAPPA 16.0
+#endif
 typedef __float128 qreal;
 
 #define ORC_MAXD 12
@@ -481,21 +489,41 @@ static cplx kernel_val(const kern_t *kk, const long double x[3], const geo_t *g)
 /* Moments of the kernel against K_nm with a rule on triangle T given by
  * vertices (in T0 coordinates); weights scaled by |T|/|T0|. */
 static void tri_moments(const patch_t *pt, const kern_t *kk, const long double x[3],
-                        const double tri[6], const double *rule, int nq, cplx *mom)
+                        const double tri[6], const double *rule, int nq, cplx *mom, double *noise2)
 {
     double ax = tri[0], ay = tri[1];
     double e1x = tri[2] - ax, e1y = tri[3] - ay, e2x = tri[4] - ax, e2y = tri[5] - ay;
     double scale = fabs(e1x * e2y - e1y * e2x); /* = |T| / |T0| */
     for (int i = 0; i < pt->nd; ++i) mom[i] = 0;
     double K[ORC_MAXND];
+    const double xx = (double)(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    const double bmag = cabs(kk->beta);
+    double g2 = 0.0;
     for (int q = 0; q < nq; ++q) {
         double u = ax + rule[3 * q] * e1x + rule[3 * q + 1] * e2x;
         double v = ay + rule[3 * q] * e1y + rule[3 * q + 1] * e2y;
         geo_t g;
         chart(pt, u, v, &g, K);
-        cplx f = kernel_val(kk, x, &g) * rule[3 * q + 2] * scale;
-        for (int i = 0; i < pt->nd; ++i) mom[i] += f * K[i];
+        const double w = rule[3 * q + 2] * scale;
+        cplx f = kernel_val(kk, x, &g) * w;
+        double kk2 = 0.0;
+        for (int i = 0; i < pt->nd; ++i) {
+            mom[i] += f * K[i];
+            kk2 += K[i] * K[i];
+        }
+        /* rounding-noise scale (in units of the double-precision unit
+         * roundoff) of this node's contribution: the sum itself (|f|), and
+         * the separation x - X, whose absolute error ~|x| moves the single
+         * layer by ~|f|/r and the double layer's numerator n.(x - X) by
+         * ~b = |beta| J w / (4 pi r^3) per unit length; squared bound
+         * |f|^2 + 2 |x|^2 (|f|^2 / r^2 + b^2), times |K|^2 */
+        const long double dl[3] = {x[0] - g.X[0], x[1] - g.X[1], x[2] - g.X[2]};
+        const double r2 = (double)(dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2]);
+        const double b = bmag * (double)g.J * w / (4.0 * ORC_PI * r2 * sqrt(r2));
+        const double fa2 = creal(f) * creal(f) + cimag(f) * cimag(f);
+        g2 += (fa2 + 2.0 * xx * (fa2 / r2 + b * b)) * kk2;
     }
+    if (noise2) *noise2 = g2;
 }
 
 static double cnorm_diff(int nd, const cplx *a, const cplx *b)
@@ -547,7 +575,7 @@ static int near_moments(const patch_t *pt, const kern_t *kk, const long double x
     node_t *stk = malloc(sizeof(node_t) * cap);
     int sp = 0;
     node_t root = {{0, 0, 1, 0, 0, 1}, 0, 0, {0}};
-    tri_moments(pt, kk, x, root.tri, rule, nq, root.I);
+    tri_moments(pt, kk, x, root.tri, rule, nq, root.I, NULL);
     st->visits += 1;
     stk[sp++] = root;
     for (int i = 0; i < nd; ++i) tot[i] = 0;
@@ -568,11 +596,14 @@ static int near_moments(const patch_t *pt, const kern_t *kk, const long double x
             {bc[0], bc[1], ca[0], ca[1], ab[0], ab[1]}};
         cplx S[ORC_MAXND];
         for (int i = 0; i < nd; ++i) S[i] = 0;
+        double noise2 = 0.0;
         for (int k = 0; k < 4; ++k) {
             memcpy(ch[k].tri, tris[k], sizeof(tris[k]));
             ch[k].depth = T.depth + 1;
             ch[k].code = T.code * 4 + (uint64_t)k;
-            tri_moments(pt, kk, x, ch[k].tri, rule, nq, ch[k].I);
+            double n2;
+            tri_moments(pt, kk, x, ch[k].tri, rule, nq, ch[k].I, &n2);
+            noise2 += n2;
             for (int i = 0; i < nd; ++i) S[i] += ch[k].I[i];
         }
         st->visits += 4;
@@ -588,6 +619,14 @@ static int near_moments(const patch_t *pt, const kern_t *kk, const long double x
             if (g > thr) thr = g;
         }
         int accept = err <= thr;
+        if (!truth) {
+            /* rounding floor: the difference is accepted at the estimated
+             * double-precision rounding level of the moments (children's
+             * noise, doubled for the parent's), which the scaled threshold
+             * of deep subtriangles near a target can fall below */
+            const double u = 0x1p-53;
+            if (err <= ORC_NOISE_KAPPA * u * sqrt(2.0 * noise2)) accept = 1;
+        }
         if (!accept && T.depth + 1 >= max_depth) { accept = 1; nonconv = 1; }
         if (accept) {
             for (int i = 0; i < nd; ++i) tot[i] += S[i];

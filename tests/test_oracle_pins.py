@@ -162,6 +162,38 @@ def test_flat_single_layer_closed_form(dist, mode):
         assert abs(a.sum() - exact) <= bound + 1e-14 * abs(exact), (t, a.sum(), exact)
 
 
+@pytest.mark.parametrize("dist", [1e-6, 1e-8])
+def test_method_rounding_floor_near_coincident(dist):
+    """Targets almost on a flat patch (above an interior point, beside an
+    edge, above a corner): the method's test reaches its double-precision
+    rounding floor there.  The trees stay small (accepted at the floor, not
+    refined to the depth limit) and the single and double layers keep the
+    Section 4.3 error bound against the closed forms (Wilton et al.;
+    Van Oosterom-Strackee)."""
+    n = np.cross(TRI[1] - TRI[0], TRI[2] - TRI[0])
+    nh = n / np.linalg.norm(n)
+    area = 0.5 * np.linalg.norm(n)
+    edge_mid = 0.5 * (TRI[0] + TRI[1])
+    out_dir = np.cross(TRI[1] - TRI[0], nh)
+    out_dir /= np.linalg.norm(out_dir)
+    targets = [TRI.mean(0) + dist * nh, edge_mid + dist * out_dir + dist * nh,
+               0.9 * TRI[2] + 0.1 * TRI.mean(0) + dist * nh]
+    tol = 1e-8
+    for al, be, exact_fn in [(1.0, 0.0, lambda x: wilton_potential(TRI, x) / (4 * math.pi)),
+                             (0.0, 1.0, lambda x: -solid_angle(TRI, x) / (4 * math.pi))]:
+        prob = flat_patch_problem(TRI, 4, targets, alpha=al, beta=be, k=0, tol=tol)
+        # depth 30: a point-like near-singularity at height h needs ~log2(1/h) levels
+        run = oracle.OracleRun(prob, mode=oracle.METHOD, max_depth=30)
+        for t, x in enumerate(targets):
+            c0 = run.stats.checks
+            a = run.pair(t, 0)
+            checks = run.stats.checks - c0
+            exact = exact_fn(x)
+            assert run.stats.nonconverged == 0
+            assert checks < 1000, (t, checks)
+            assert abs(a.sum() - exact) <= 10 * tol * math.sqrt(area), (al, be, t, a.sum(), exact)
+
+
 @pytest.mark.parametrize("dist", [1.0, 1e-1, 1e-2, 1e-3])
 def test_flat_double_layer_solid_angle(dist):
     """Laplace double layer n.grad_y G_0 of a flat patch: sum_l a_l(x) equals
