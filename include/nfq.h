@@ -106,7 +106,9 @@ typedef struct {
  * subdivision (pairs reaching it are counted as non-converged).
  * ng: points per direction of the subtriangle rule (0 = default 8; only 8 is
  * supported).  self_nr / self_na: radial / angular Gauss-Legendre sizes of
- * the self rule (0 = defaults 10 / 16). */
+ * the self rule per panel, at most 64 (0 = per-degree defaults: 10 / 16 for
+ * degree <= 3, 14 / 20 for 4, 16 / 24 for 5, 18 / 28 for 6 and 7, 20 / 32
+ * for 8). */
 typedef struct {
     double tol;
     double loosen;

@@ -401,6 +401,7 @@ typedef struct {
     long double coef[3][ORC_MAXND];
     const orc_ref *ref;
     double dj;   /* min_l sqrt(J(u_l,v_l) |w_l|) (Section 4.2) */
+    double rho;  /* max_l |x_l|: coordinate scale of the patch */
 } patch_t;
 
 /* Chart X = sum_nm x_nm K_nm, its derivatives, n = X_u x X_v and J = |n|
@@ -466,6 +467,12 @@ static int setup_patch(const orc_problem *pb, int64_t j, patch_t *pt)
         if (q < dj) dj = q;
     }
     pt->dj = dj;
+    double rho = 0.0;
+    for (int l = 0; l < r->nd; ++l) {
+        const double nx = sqrt(x[3 * l] * x[3 * l] + x[3 * l + 1] * x[3 * l + 1] + x[3 * l + 2] * x[3 * l + 2]);
+        if (nx > rho) rho = nx;
+    }
+    pt->rho = rho;
     return 0;
 }
 
@@ -496,7 +503,6 @@ static void tri_moments(const patch_t *pt, const kern_t *kk, const long double x
     double scale = fabs(e1x * e2y - e1y * e2x); /* = |T| / |T0| */
     for (int i = 0; i < pt->nd; ++i) mom[i] = 0;
     double K[ORC_MAXND];
-    const double xx = (double)(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
     const double bmag = cabs(kk->beta);
     double g2 = 0.0;
     for (int q = 0; q < nq; ++q) {
@@ -511,17 +517,16 @@ static void tri_moments(const patch_t *pt, const kern_t *kk, const long double x
             mom[i] += f * K[i];
             kk2 += K[i] * K[i];
         }
-        /* rounding-noise scale (in units of the double-precision unit
-         * roundoff) of this node's contribution: the sum itself (|f|), and
-         * the separation x - X, whose absolute error ~|x| moves the single
-         * layer by ~|f|/r and the double layer's numerator n.(x - X) by
-         * ~b = |beta| J w / (4 pi r^3) per unit length; squared bound
-         * |f|^2 + 2 |x|^2 (|f|^2 / r^2 + b^2), times |K|^2 */
+        /* sensitivity of this node's contribution to the separation
+         * x - X (whose rounding error scales with the coordinates): the
+         * single layer moves by ~|f|/r and the double layer's numerator
+         * n.(x - X) by ~b = |beta| J w / (4 pi r^3) per unit length;
+         * (|f|^2 / r^2 + b^2) |K|^2 */
         const long double dl[3] = {x[0] - g.X[0], x[1] - g.X[1], x[2] - g.X[2]};
         const double r2 = (double)(dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2]);
         const double b = bmag * (double)g.J * w / (4.0 * ORC_PI * r2 * sqrt(r2));
         const double fa2 = creal(f) * creal(f) + cimag(f) * cimag(f);
-        g2 += (fa2 + 2.0 * xx * (fa2 / r2 + b * b)) * kk2;
+        g2 += (fa2 / r2 + b * b) * kk2;
     }
     if (noise2) *noise2 = g2;
 }
@@ -621,11 +626,13 @@ static int near_moments(const patch_t *pt, const kern_t *kk, const long double x
         int accept = err <= thr;
         if (!truth) {
             /* rounding floor: the difference is accepted at the estimated
-             * double-precision rounding level of the moments (children's
-             * noise, doubled for the parent's), which the scaled threshold
-             * of deep subtriangles near a target can fall below */
+             * double-precision rounding level of the moments, which the
+             * scaled threshold of deep subtriangles near a target can fall
+             * below: u (|x| + rho_j) times the children's sensitivities,
+             * doubled for the parent's and for the squared bound */
             const double u = 0x1p-53;
-            if (err <= ORC_NOISE_KAPPA * u * sqrt(2.0 * noise2)) accept = 1;
+            const double sc = (double)sqrtl(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) + pt->rho;
+            if (err <= ORC_NOISE_KAPPA * u * sc * 2.0 * sqrt(noise2)) accept = 1;
         }
         if (!accept && T.depth + 1 >= max_depth) { accept = 1; nonconv = 1; }
         if (accept) {

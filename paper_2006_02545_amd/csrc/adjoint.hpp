@@ -218,16 +218,6 @@ __device__ __forceinline__ void sigma_at(const double *sc, const double *K, doub
     }
 }
 
-// Sum over the wavefront, into every lane (row sums by rotation, then the
-// four rows).
-__device__ __forceinline__ double wave_total(double v)
-{
-    v = row_sum16(v);
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    return v;
-}
-
 // Adjoint of the near quadrature, one work item (patch, <= 64 targets) per
 // workgroup.  The forward's subdivision walk is replayed with its own
 // arithmetic (same work split, same tests).  After the test of a group, the
@@ -243,7 +233,7 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
 {
     using S = PatchShape<D, true>;
     constexpr int ND = S::ND, W = S::W, PL = S::PL, G0 = S::G0, KS = S::KS, R = S::R;
-    constexpr int GSA = (KS + 7 + 6) | 1;   // forward row + X_u, X_v
+    constexpr int GSA = (KS + 8 + 6) | 1;   // forward row + X_u, X_v
     const PatchArgs &a = aa.pa;
     __shared__ double s_geo[256 * GSA];
     __shared__ GroupEntry s_stack[kGroupStack];
@@ -255,6 +245,7 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
     __shared__ double s_sc[2 * KS];
     __shared__ double s_cf[3 * ND];
     __shared__ double s_cm[4 * W];
+    __shared__ double s_g2[4];
     __shared__ unsigned long long s_fail;
     __shared__ int s_sp;
 
@@ -273,6 +264,12 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
         for (int k = tid; k < 2 * KS; k += 256) s_sc[k] = k < 2 * ND ? aa.scoef[2 * nb + k] : 0.0;
         const double *cf = s_cf;
         const double tau = a.tau[j];
+        const double rho_j = a.rho[j];
+        auto nfac = [&](int s) {
+            return noise_factor(__builtin_sqrt(s_x[s][0] * s_x[s][0] + s_x[s][1] * s_x[s][1] +
+                                               s_x[s][2] * s_x[s][2]) + rho_j);
+        };
+        unsigned item_groups = 0;
         if (tid < count) {
             const int p = a.plist[start + tid];
             const int64_t t = a.pair_tgt[p];
@@ -296,8 +293,8 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
 #pragma unroll
             for (int v = 0; v < W; ++v) acc[v] = 0.0;
             const double *g = s_geo + lane * GSA;
-            double fr, fi;
-            kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
+            double fr, fi, sn;
+            kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular, sn);
             mac_node<D, true>(acc, g, fr, fi);
             rot_reduce16<PL>(acc);
 #pragma unroll
@@ -333,6 +330,7 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                 s_sp = s_sp - 1;
                 s_fail = 0ull;
             }
+            const bool capped = ++item_groups > kGroupCap;
             const double ax = e.tri[0], ay = e.tri[1], bx = e.tri[2], by = e.tri[3];
             const double cx = e.tri[4], cy = e.tri[5];
             const double abx = 0.5 * (ax + bx), aby = 0.5 * (ay + by);
@@ -367,12 +365,15 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                 double acc[W];
 #pragma unroll
                 for (int v = 0; v < W; ++v) acc[v] = 0.0;
+                double sens;
                 {
                     const double *g = s_geo + tid * GSA;
                     double fr, fi;
-                    kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
+                    kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular, sens);
                     mac_node<D, true>(acc, g, fr, fi);
                 }
+                sens = wave_total(sens);
+                if (lane == 0) s_g2[wv] = sens;
                 rot_reduce16<PL>(acc);
                 double cm[PL];
 #pragma unroll
@@ -392,8 +393,9 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                     e2 = __builtin_fma(df, df, e2);
                 }
                 const double err2 = lane0(row_sum16(e2));
-                bool accept = err2 <= thr * thr && L + 1 >= a.min_depth;
-                if (!accept && L + 1 >= a.max_depth) accept = true;
+                const double noise2 = nfac(s) * ((s_g2[0] + s_g2[1]) + (s_g2[2] + s_g2[3]));
+                bool accept = (err2 <= thr * thr || err2 <= noise2) && L + 1 >= a.min_depth;
+                if (!accept && (L + 1 >= a.max_depth || capped)) accept = true;
                 if (!accept) {
                     if (grp16 == 0) {
                         double *dst = mptr(L + 1, wv, s);
@@ -419,13 +421,16 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                     double acc[W];
 #pragma unroll
                     for (int v = 0; v < W; ++v) acc[v] = 0.0;
+                    double sens = 0.0;
 #pragma unroll 1
                     for (int i = 0; i < 4; ++i) {
                         const double *g = s_geo + (grp16 * 64 + l16 + 16 * i) * GSA;
-                        double fr, fi;
-                        kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
+                        double fr, fi, sn;
+                        kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular, sn);
                         mac_node<D, true>(acc, g, fr, fi);
+                        sens += sn;
                     }
+                    const double noise2 = nfac(s) * wave_total(sens);
                     rot_reduce16<PL>(acc);
                     double e2 = 0.0;
 #pragma unroll
@@ -436,8 +441,8 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                         e2 = __builtin_fma(df, df, e2);
                     }
                     const double err2 = lane0(row_sum16(e2));
-                    bool accept = err2 <= thr * thr && L + 1 >= a.min_depth;
-                    if (!accept && L + 1 >= a.max_depth) accept = true;
+                    bool accept = (err2 <= thr * thr || err2 <= noise2) && L + 1 >= a.min_depth;
+                    if (!accept && (L + 1 >= a.max_depth || capped)) accept = true;
                     if (!accept) {
                         double *dst = mptr(L + 1, grp16, s);
 #pragma unroll
@@ -452,8 +457,8 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
             if (accm != 0ull) {
                 const double *g = s_geo + tid * GSA;
                 const double X[3] = {g[G0], g[G0 + 1], g[G0 + 2]};
-                const double Xu[3] = {g[G0 + 7], g[G0 + 8], g[G0 + 9]};
-                const double Xv[3] = {g[G0 + 10], g[G0 + 11], g[G0 + 12]};
+                const double Xu[3] = {g[G0 + 8], g[G0 + 9], g[G0 + 10]};
+                const double Xv[3] = {g[G0 + 11], g[G0 + 12], g[G0 + 13]};
                 const double n[3] = {Xu[1] * Xv[2] - Xu[2] * Xv[1], Xu[2] * Xv[0] - Xu[0] * Xv[2],
                                      Xu[0] * Xv[1] - Xu[1] * Xv[0]};
                 const double wq = a.rule[3 * (tid & 63) + 2] * area;
@@ -666,8 +671,10 @@ __global__ __launch_bounds__(64) void k_adjoint_self(AdjArgs aa)
                     hl = phl[k]; det = pdet[k]; xa = pxa[k]; xb = pxb[k];
                 }
             const double xi = xa + (xb - xa) * a.gla[2 * ia];
-            const double lam = mu + hl * sinh(xi);
-            const double dlam = hl * cosh(xi) * (xb - xa) * a.gla[2 * ia + 1];
+            // sinh and cosh from one exponential (lam needs absolute accuracy)
+            const double ex = exp(xi), exi = 1.0 / ex;
+            const double lam = mu + hl * (0.5 * (ex - exi));
+            const double dlam = hl * (0.5 * (ex + exi)) * (xb - xa) * a.gla[2 * ia + 1];
             const double s = a.glr[2 * ir], ws = a.glr[2 * ir + 1];
             const double dx = Ax + lam * Ex - tu, dy = Ay + lam * Ey - tv;
             double K[ND], Ku[ND], Kv[ND], X[3], Xu[3], Xv[3];

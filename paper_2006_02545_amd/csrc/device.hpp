@@ -14,7 +14,24 @@ constexpr double kInv4Pi = 0.079577471545947667884441881686257181;  // 1/(4 pi)
 
 struct Kern {
     double ar, ai, br, bi, kr, ki;  // alpha, beta, wavenumber
+    double bm;                      // |beta|
 };
+
+// Rounding floor of the adaptive test.  A node's moment contribution moves
+// by about (|f|/r + b) |dX| when the separation x - X(y) is off by |dX|
+// (b = |beta| J w / (4 pi r^3) for the double layer's numerator), and |dX|
+// is a few units of roundoff times the coordinate scale |x| + max_l |x_l|.
+// A test whose difference lies below kNoiseKappa times that level, summed
+// in quadrature over the children's nodes (doubled for the parent and for
+// the squared bound), is accepted: refining further cannot reduce it.
+constexpr double kNoiseKappa = 16.0;
+constexpr double kUnitRoundoff = 0x1p-53;
+
+__device__ __forceinline__ double noise_factor(double scale)
+{
+    const double g = 2.0 * kNoiseKappa * kUnitRoundoff * scale;
+    return g * g;
+}
 
 // Values of the Koornwinder basis at (u,v) into K[ND], and the chart
 // X = sum_a coef[c*ND + a] K_a with its derivatives (Section 3.2).
@@ -43,7 +60,7 @@ __device__ __forceinline__ void chart_eval(const double *__restrict__ coef, doub
 // Returns (re, im).  `helm` selects the Helmholtz path (k != 0).
 __device__ __forceinline__ void kern_eval(const Kern &k, bool helm, const double x[3],
                                           const double y[3], const double n[3], double &fr,
-                                          double &fi, int &singular)
+                                          double &fi, int &singular, double &sens)
 {
     const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
     const double r2 = dx * dx + dy * dy + dz * dz;
@@ -53,10 +70,13 @@ __device__ __forceinline__ void kern_eval(const Kern &k, bool helm, const double
     const double nd = n[0] * dx + n[1] * dy + n[2] * dz;
     const double g0 = kInv4Pi * rinv;            // 1/(4 pi r)
     const double d0 = g0 * nd * rinv * rinv;     // n.(x-y)/(4 pi r^3)
+    const double rinv2 = rinv * rinv;
+    const double bsens = k.bm * g0 * J * rinv2;  // |beta| J / (4 pi r^3)
     if (!helm) {
         // e^{ikr} = 1, (1 - ikr) = 1
         fr = k.ar * g0 * J + k.br * d0;
         fi = k.ai * g0 * J + k.bi * d0;
+        sens = (fr * fr + fi * fi) * rinv2 + bsens * bsens;
         return;
     }
     const double r = r2 * rinv;
@@ -74,6 +94,15 @@ __device__ __forceinline__ void kern_eval(const Kern &k, bool helm, const double
     const double qr = d0 * (pr * c - pi * s), qi = d0 * (pr * s + pi * c);
     fr = k.ar * gr - k.ai * gi + k.br * qr - k.bi * qi;
     fi = k.ar * gi + k.ai * gr + k.br * qi + k.bi * qr;
+    sens = (fr * fr + fi * fi) * rinv2 + bsens * bsens;
+}
+
+__device__ __forceinline__ void kern_eval(const Kern &k, bool helm, const double x[3],
+                                          const double y[3], const double n[3], double &fr,
+                                          double &fi, int &singular)
+{
+    double sens;
+    kern_eval(k, helm, x, y, n, fr, fi, singular, sens);
 }
 
 __device__ __forceinline__ double wave_sum(double v)

@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_group(int64_t np, const int32_t *pair_p
 
 template <int D>
 __device__ void prep_patch(const Problem &pb, const DegTab &tab, int64_t j, double tol_scale,
-                           double *coef, double *tau, int *flags)
+                           double *coef, double *tau, double *rho, int *flags)
 {
     constexpr int ND = nd_of(D);
     const double *V = tab.V[D];
@@ -279,22 +279,27 @@ __device__ void prep_patch(const Problem &pb, const DegTab &tab, int64_t j, doub
     }
     if (bad) flags[kFlagDegenerate] = 1;
     tau[j] = tol_scale * dj / tab.normV[D];
+    double rh = 0.0;
+    for (int l = 0; l < ND; ++l)
+        rh = __builtin_fmax(rh, __builtin_sqrt(x[3 * l] * x[3 * l] + x[3 * l + 1] * x[3 * l + 1] +
+                                               x[3 * l + 2] * x[3 * l + 2]));
+    rho[j] = rh;
 }
 
 __global__ void k_prep(Problem pb, DegTab tab, double tol_scale, double *coef, double *tau,
-                       int *flags)
+                       double *rho, int *flags)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= pb.P) return;
     switch (pb.degree[j]) {
-    case 1: prep_patch<1>(pb, tab, j, tol_scale, coef, tau, flags); break;
-    case 2: prep_patch<2>(pb, tab, j, tol_scale, coef, tau, flags); break;
-    case 3: prep_patch<3>(pb, tab, j, tol_scale, coef, tau, flags); break;
-    case 4: prep_patch<4>(pb, tab, j, tol_scale, coef, tau, flags); break;
-    case 5: prep_patch<5>(pb, tab, j, tol_scale, coef, tau, flags); break;
-    case 6: prep_patch<6>(pb, tab, j, tol_scale, coef, tau, flags); break;
-    case 7: prep_patch<7>(pb, tab, j, tol_scale, coef, tau, flags); break;
-    case 8: prep_patch<8>(pb, tab, j, tol_scale, coef, tau, flags); break;
+    case 1: prep_patch<1>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
+    case 2: prep_patch<2>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
+    case 3: prep_patch<3>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
+    case 4: prep_patch<4>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
+    case 5: prep_patch<5>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
+    case 6: prep_patch<6>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
+    case 7: prep_patch<7>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
+    case 8: prep_patch<8>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
     default: flags[kFlagNotRegistered] = 1; break;
     }
 }
@@ -318,6 +323,7 @@ struct QuadArgs {
     const int64_t *pair_off;
     const double *coef;
     const double *tau;
+    const double *rho;    // max_l |x_l| per patch (coordinate scale)
     double *val;
     double *stack;        // near: [waves][kStack][entry]
     int *flags;
@@ -403,6 +409,8 @@ __global__ __launch_bounds__((64 * QuadShape<D, CPLX>::WPB)) void k_near(QuadArg
         const double x[3] = {a.pb.txyz[3 * (int64_t)t], a.pb.txyz[3 * (int64_t)t + 1],
                              a.pb.txyz[3 * (int64_t)t + 2]};
         const double tau = a.tau[j];
+        const double nfac = noise_factor(__builtin_sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) +
+                                         a.rho[j]);
         ++st_pairs;
         // root: one node per lane
         double acc[NV];
@@ -465,6 +473,7 @@ __global__ __launch_bounds__((64 * QuadShape<D, CPLX>::WPB)) void k_near(QuadArg
             const double area = __builtin_ldexp(1.0, -2 * (depth + 1));  // |C| / |T0|
 #pragma unroll
             for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+            double sens = 0.0;
 #pragma unroll 1
             for (int i = 0; i < 4; ++i) {
                 const int q = (lane & 15) + 16 * i;
@@ -475,11 +484,16 @@ __global__ __launch_bounds__((64 * QuadShape<D, CPLX>::WPB)) void k_near(QuadArg
                 chart_eval<D>(cf, u, v, K, X, Xu, Xv);
                 const double n[3] = {Xu[1] * Xv[2] - Xu[2] * Xv[1], Xu[2] * Xv[0] - Xu[0] * Xv[2],
                                      Xu[0] * Xv[1] - Xu[1] * Xv[0]};
-                double fr, fi;
-                kern_eval(a.kern, a.helm, x, X, n, fr, fi, singular);
+                double fr, fi, sn;
+                kern_eval(a.kern, a.helm, x, X, n, fr, fi, singular, sn);
                 const double w = rw * area;
                 acc_products<ND, CPLX>(acc, K, fr * w, fi * w);
+                double kk2 = 0.0;
+#pragma unroll
+                for (int m = 0; m < ND; ++m) kk2 = __builtin_fma(K[m], K[m], kk2);
+                sens = __builtin_fma(sn * w * w, kk2, sens);
             }
+            const double noise2 = nfac * wave_sum(sens);
             lds_group_reduce<NV, NVP, 16>(red, out, acc, lane);
             // out[c * NV + v] = component v of the moments of child c
             double Sv[NL], e2 = 0.0;
@@ -494,7 +508,7 @@ __global__ __launch_bounds__((64 * QuadShape<D, CPLX>::WPB)) void k_near(QuadArg
             const double thr = tau * __builtin_ldexp(1.0, -2 * depth);
             st_visits += 4;
             ++st_checks;
-            const bool ok = err2 <= thr * thr;
+            const bool ok = err2 <= thr * thr || err2 <= noise2;
             bool accept = ok && depth + 1 >= a.min_depth;
             if (!accept && (depth + 1 >= a.max_depth || sp + 4 > kStack)) {
                 if (sp + 4 > kStack) overflow = 1;
@@ -660,8 +674,10 @@ __global__ __launch_bounds__((64 * SelfShape<D, CPLX>::WPB)) void k_self(QuadArg
                 const double Ax = pp[0], Ay = pp[1], Ex = pp[2], Ey = pp[3], mu = pp[4];
                 const double hl = pp[5], det = pp[6], xa = pp[7], xb = pp[8];
                 const double xi = xa + (xb - xa) * a.gla[2 * ia];
-                const double lam = mu + hl * sinh(xi);
-                const double dlam = hl * cosh(xi) * (xb - xa) * a.gla[2 * ia + 1];
+                // sinh and cosh from one exponential (lam needs absolute accuracy)
+                const double ex = exp(xi), exi = 1.0 / ex;
+                const double lam = mu + hl * (0.5 * (ex - exi));
+                const double dlam = hl * (0.5 * (ex + exi)) * (xb - xa) * a.gla[2 * ia + 1];
                 const double s = a.glr[2 * ir], ws = a.glr[2 * ir + 1];
                 const double dx = Ax + lam * Ex - tu, dy = Ay + lam * Ey - tv;
                 double X[3], Xu[3], Xv[3];

@@ -41,8 +41,8 @@ struct PatchShape {
     static constexpr int KS = 16 * R;                // basis slots per node
     static constexpr int PL = R * C;                 // doubles per lane after the reduce-scatter
     static constexpr int W = 16 * PL;                // doubles per lane before it
-    static constexpr int GS = (KS + 7) | 1;          // LDS doubles per node (odd pitch)
-    static constexpr int G0 = KS;                    // y, n w, J w follow the basis slots
+    static constexpr int GS = (KS + 8) | 1;          // LDS doubles per node (odd pitch)
+    static constexpr int G0 = KS;                    // y, n w, J w, |K|^2 follow the basis slots
     // per-target totals kept in LDS when they fit beside the geometry
     static constexpr bool TOT_LDS = (64 * NV + 256 * GS) * 8 <= 140 * 1024;
     static constexpr int TOTN = TOT_LDS ? 64 * NV : 1;
@@ -69,6 +69,7 @@ struct PatchArgs {
     const int64_t *pair_off;
     const double *coef;
     const double *tau;
+    const double *rho;        // max_l |x_l| per patch (coordinate scale)
     double *val;
     double *mom;              // per workgroup slot: [max_depth + 1][4][64][W]
     int64_t mom_slot;         // doubles per slot
@@ -142,10 +143,14 @@ __device__ __forceinline__ void node_geometry(const double *cf, double Ax, doubl
     g[G0 + 0] = X[0]; g[G0 + 1] = X[1]; g[G0 + 2] = X[2];
     g[G0 + 3] = n0 * wgt; g[G0 + 4] = n1 * wgt; g[G0 + 5] = n2 * wgt;
     g[G0 + 6] = __builtin_sqrt(n0 * n0 + n1 * n1 + n2 * n2) * wgt;
+    double kk2 = 0.0;
+#pragma unroll
+    for (int m = 0; m < ND; ++m) kk2 = __builtin_fma(K[m], K[m], kk2);
+    g[G0 + 7] = kk2;
     if (DERIV) {
         // chart derivatives for the adjoint
-        g[G0 + 7] = Xu[0]; g[G0 + 8] = Xu[1]; g[G0 + 9] = Xu[2];
-        g[G0 + 10] = Xv[0]; g[G0 + 11] = Xv[1]; g[G0 + 12] = Xv[2];
+        g[G0 + 8] = Xu[0]; g[G0 + 9] = Xu[1]; g[G0 + 10] = Xu[2];
+        g[G0 + 11] = Xv[0]; g[G0 + 12] = Xv[1]; g[G0 + 13] = Xv[2];
     }
     int rot = (16 - l16) & 15;
     // keep the slot addresses local to this call (hoisting them out of the
@@ -177,19 +182,24 @@ __device__ __forceinline__ void mac_node(double *acc, const double *g, double fr
 
 // Weighted kernel value at a node whose geometry g carries n w and J w.
 __device__ __forceinline__ void kern_node(const Kern &k, bool helm, const double x[3],
-                                          const double *g, double &fr, double &fi, int &singular)
+                                          const double *g, double &fr, double &fi, int &singular,
+                                          double &sens)
 {
-    // g points at the node's y, n w, J w
+    // g points at the node's y, n w, J w, |K|^2; sens: rounding sensitivity
+    // (|f|^2 / r^2 + b^2) |K|^2 of the weighted value (see kNoiseKappa)
     const double dx = x[0] - g[0], dy = x[1] - g[1], dz = x[2] - g[2];
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (r2 == 0.0) singular = 1;
     const double rinv = rsqrt_nr(r2);
     const double g0 = kInv4Pi * rinv;
     const double gJ = g0 * g[6];
-    const double d0 = g0 * (g[3] * dx + g[4] * dy + g[5] * dz) * rinv * rinv;
+    const double rinv2 = rinv * rinv;
+    const double d0 = g0 * (g[3] * dx + g[4] * dy + g[5] * dz) * rinv2;
+    const double bs = k.bm * gJ * rinv2;
     if (!helm) {
         fr = k.ar * gJ + k.br * d0;
         fi = k.ai * gJ + k.bi * d0;
+        sens = ((fr * fr + fi * fi) * rinv2 + bs * bs) * g[7];
         return;
     }
     const double r = r2 * rinv;
@@ -205,7 +215,23 @@ __device__ __forceinline__ void kern_node(const Kern &k, bool helm, const double
     const double qr = d0 * (pr * c - pi * s), qi = d0 * (pr * s + pi * c);
     fr = k.ar * gr - k.ai * gi + k.br * qr - k.bi * qi;
     fi = k.ar * gi + k.ai * gr + k.br * qi + k.bi * qr;
+    sens = ((fr * fr + fi * fi) * rinv2 + bs * bs) * g[7];
 }
+
+// Sum over the wavefront, into every lane (row sums by rotation, then the
+// four rows).
+__device__ __forceinline__ double wave_total(double v)
+{
+    v = row_sum16(v);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// Largest number of subdivision groups one work item may take; beyond it the
+// remaining tests accept (and count as non-converged).  It bounds the walk
+// far above any converging tree.
+constexpr unsigned kGroupCap = 1u << 18;
 
 struct GroupEntry {
     double tri[6];
@@ -227,6 +253,7 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
     __shared__ int64_t s_off[64];
     __shared__ double s_cf[3 * S::ND];
     __shared__ double s_cm[4 * W];
+    __shared__ double s_g2[4];
     __shared__ unsigned long long s_fail;
     __shared__ int s_sp;
 
@@ -246,6 +273,13 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
         for (int k = tid; k < 3 * S::ND; k += 256) s_cf[k] = a.coef[3 * a.pb.node_ptr[j] + k];
         const double *cf = s_cf;
         const double tau = a.tau[j];
+        const double rho_j = a.rho[j];
+        // rounding-floor factor of target s (see kNoiseKappa)
+        auto nfac = [&](int s) {
+            return noise_factor(__builtin_sqrt(s_x[s][0] * s_x[s][0] + s_x[s][1] * s_x[s][1] +
+                                               s_x[s][2] * s_x[s][2]) + rho_j);
+        };
+        unsigned item_groups = 0;
         if (tid < count) {
             const int p = a.plist[start + tid];
             const int64_t t = a.pair_tgt[p];
@@ -273,8 +307,8 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
 #pragma unroll
             for (int v = 0; v < W; ++v) acc[v] = 0.0;
             const double *g = s_geo + lane * GS;
-            double fr, fi;
-            kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
+            double fr, fi, sn;
+            kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular, sn);
             mac_node<D, CPLX>(acc, g, fr, fi);
             rot_reduce16<PL>(acc);
 #pragma unroll
@@ -307,6 +341,7 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                 s_sp = s_sp - 1;
                 s_fail = 0ull;
             }
+            const bool capped = ++item_groups > kGroupCap;
             // children geometry: thread tid -> child tid / 64, node tid % 64,
             // read by row lane tid % 16
             const double ax = e.tri[0], ay = e.tri[1], bx = e.tri[2], by = e.tri[3];
@@ -346,12 +381,15 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                 double acc[W];
 #pragma unroll
                 for (int v = 0; v < W; ++v) acc[v] = 0.0;
+                double sens;
                 {
                     const double *g = s_geo + tid * GS;
                     double fr, fi;
-                    kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
+                    kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular, sens);
                     mac_node<D, CPLX>(acc, g, fr, fi);
                 }
+                sens = wave_total(sens);
+                if (lane == 0) s_g2[wv] = sens;
                 rot_reduce16<PL>(acc);
                 double cm[PL];
 #pragma unroll
@@ -373,13 +411,14 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                     e2 = __builtin_fma(df, df, e2);
                 }
                 const double err2 = lane0(row_sum16(e2));
+                const double noise2 = nfac(s) * ((s_g2[0] + s_g2[1]) + (s_g2[2] + s_g2[3]));
                 if (mine) {
                     ++st_checks;
                     st_visits += 4;
                 }
-                const bool ok = err2 <= thr * thr;
+                const bool ok = err2 <= thr * thr || err2 <= noise2;
                 bool accept = ok && L + 1 >= a.min_depth;
-                if (!accept && L + 1 >= a.max_depth) {
+                if (!accept && (L + 1 >= a.max_depth || capped)) {
                     accept = true;
                     if (!ok && mine) ++st_nonconv;
                 }
@@ -420,13 +459,16 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                     double acc[W];
 #pragma unroll
                     for (int v = 0; v < W; ++v) acc[v] = 0.0;
+                    double sens = 0.0;
 #pragma unroll 1
                     for (int i = 0; i < 4; ++i) {
                         const double *g = s_geo + (grp16 * 64 + l16 + 16 * i) * GS;
-                        double fr, fi;
-                        kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular);
+                        double fr, fi, sn;
+                        kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular, sn);
                         mac_node<D, CPLX>(acc, g, fr, fi);
+                        sens += sn;
                     }
+                    const double noise2 = nfac(s) * wave_total(sens);
                     rot_reduce16<PL>(acc);
                     // acc[0..PL): unit l16 of child grp16's moments; the sum over
                     // the four children by two more exchanges
@@ -444,9 +486,9 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                     const double err2 = lane0(row_sum16(e2));
                     ++st_checks;
                     st_visits += 4;
-                    const bool ok = err2 <= thr * thr;
+                    const bool ok = err2 <= thr * thr || err2 <= noise2;
                     bool accept = ok && L + 1 >= a.min_depth;
-                    if (!accept && L + 1 >= a.max_depth) {
+                    if (!accept && (L + 1 >= a.max_depth || capped)) {
                         accept = true;
                         if (!ok) ++st_nonconv;
                     }
@@ -533,6 +575,34 @@ __global__ void k_patch_scatter(int64_t np, const int32_t *pair_patch, const int
     const int j = pair_patch[p];
     const unsigned long long k = atomicAdd(&pcursor[j], 1ull);
     plist[pptr[j] + (int64_t)k] = (int32_t)p;
+}
+
+// Each patch's near pairs in ascending pair order (that is, by target): the
+// scatter above places them in arrival order, and the composition of the
+// 64-target work items (hence which tests run split over four wavefronts)
+// must not depend on it.  One workgroup per patch; rank sort, from LDS when
+// the list fits.
+constexpr int kSortLds = 4096;
+
+__global__ __launch_bounds__(256) void k_patch_sort(int64_t P, const int64_t *pptr,
+                                                    const int64_t *pcount, const int32_t *raw,
+                                                    int32_t *plist)
+{
+    __shared__ int32_t s_v[kSortLds];
+    for (int64_t j = blockIdx.x; j < P; j += gridDim.x) {
+        const int64_t n = pcount[j], b = pptr[j];
+        const bool lds = n <= kSortLds;
+        if (lds)
+            for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s_v[i] = raw[b + i];
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const int32_t v = lds ? s_v[i] : raw[b + i];
+            int64_t rank = 0;
+            for (int64_t k = 0; k < n; ++k) rank += (lds ? s_v[k] : raw[b + k]) < v;
+            plist[b + rank] = v;
+        }
+        __syncthreads();
+    }
 }
 
 // Work items (patch, start, count <= 64) into per-degree segments.  Block-

@@ -22,8 +22,7 @@ struct nfq_ctx {
     RefData ref[9];
     double *dV[9] = {}, *duv[9] = {}, *dw[9] = {}, *dD[9] = {};
     double *drule = nullptr;         // [64][3]
-    double *dglr = nullptr, *dgla = nullptr;
-    int nr = 0, na = 0;
+    double *dgl = nullptr;   // Gauss-Legendre rules 1..64 on [0,1]
     std::string err;
 };
 
@@ -44,7 +43,7 @@ struct nfq_plan {
     int64_t seg_start_h[18] = {}, seg_len_h[18] = {}, count_h[18] = {};
     int64_t *seg_start = nullptr;
     unsigned long long *cursor = nullptr;
-    double *coef = nullptr, *tau = nullptr;
+    double *coef = nullptr, *tau = nullptr, *rho = nullptr;
     double *stack = nullptr;
     int64_t stack_waves = 0;
     int *flags = nullptr;
@@ -58,7 +57,7 @@ struct nfq_plan {
     int64_t n_near = 0;
     int64_t *pcount = nullptr, *nchunk = nullptr, *pptr = nullptr, *cptr = nullptr;
     unsigned long long *pcursor = nullptr;
-    int32_t *plist = nullptr;
+    int32_t *plist = nullptr, *plist_raw = nullptr;
     int32_t *items = nullptr;
     int64_t item_start_h[9] = {}, item_count_h[9] = {}, n_items = 0;
     int64_t *item_start = nullptr;
@@ -214,7 +213,10 @@ nfq_status build_items(nfq_plan *pl, hipStream_t st)
     if (s != NFQ_OK) return s;
     if (np > 0)
         hipLaunchKernelGGL(k_patch_scatter, dim3(nblk(np, 256)), dim3(256), 0, st, np, pl->pair_patch,
-                           pl->pair_self, pl->pptr, pl->pcursor, pl->plist);
+                           pl->pair_self, pl->pptr, pl->pcursor, pl->plist_raw);
+    if (np > 0)
+        hipLaunchKernelGGL(k_patch_sort, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(P, 1), 65535)),
+                           dim3(256), 0, st, P, pl->pptr, pl->pcount, pl->plist_raw, pl->plist);
     hipLaunchKernelGGL(k_items, dim3(nblk(P, 256)), dim3(256), 0, st, P, pl->pb.degree, pl->pcount,
                        pl->pptr, pl->item_start, pl->item_cursor, pl->items);
     HIP_TRY(ctx, hipGetLastError());
@@ -305,27 +307,39 @@ void launch_degree(int d, const nfq_plan *pl, const QuadArgs &qa, int64_t ns, in
     }
 }
 
-nfq_status ensure_self_rule(nfq_ctx *ctx, int nr, int na)
+// Gauss-Legendre rules on [0,1] with n = 1..kMaxGL points, rule n at pairs
+// [n (n - 1) / 2, n (n + 1) / 2) of ctx->dgl as (node, weight).
+constexpr int kMaxGL = 64;
+inline int64_t gl_offset(int n) { return (int64_t)n * (n - 1); }  // in doubles
+
+nfq_status upload_gauss_rules(nfq_ctx *ctx)
 {
-    if (ctx->nr == nr && ctx->na == na && ctx->dglr) return NFQ_OK;
-    std::vector<double> x, w;
-    std::vector<double> buf;
-    if (ctx->dglr) (void)hipFree(ctx->dglr);
-    if (ctx->dgla) (void)hipFree(ctx->dgla);
-    ctx->dglr = ctx->dgla = nullptr;
-    gauss_rule(nr, 0, 0, x, w);
-    buf.resize(2 * nr);
-    for (int i = 0; i < nr; ++i) { buf[2 * i] = x[i]; buf[2 * i + 1] = w[i]; }
-    HIP_TRY(ctx, dalloc(&ctx->dglr, buf.size()));
-    HIP_TRY(ctx, hipMemcpy(ctx->dglr, buf.data(), buf.size() * 8, hipMemcpyHostToDevice));
-    gauss_rule(na, 0, 0, x, w);
-    buf.resize(2 * na);
-    for (int i = 0; i < na; ++i) { buf[2 * i] = x[i]; buf[2 * i + 1] = w[i]; }
-    HIP_TRY(ctx, dalloc(&ctx->dgla, buf.size()));
-    HIP_TRY(ctx, hipMemcpy(ctx->dgla, buf.data(), buf.size() * 8, hipMemcpyHostToDevice));
-    ctx->nr = nr;
-    ctx->na = na;
+    std::vector<double> buf((size_t)kMaxGL * (kMaxGL + 1)), x, w;
+    for (int n = 1; n <= kMaxGL; ++n) {
+        gauss_rule(n, 0, 0, x, w);
+        for (int i = 0; i < n; ++i) {
+            buf[gl_offset(n) + 2 * i] = x[i];
+            buf[gl_offset(n) + 2 * i + 1] = w[i];
+        }
+    }
+    HIP_TRY(ctx, dalloc(&ctx->dgl, buf.size()));
+    HIP_TRY(ctx, hipMemcpy(ctx->dgl, buf.data(), buf.size() * 8, hipMemcpyHostToDevice));
     return NFQ_OK;
+}
+
+// Radial x angular sizes of the self rule per degree (Gauss-Legendre points
+// per panel), unless the caller sets them: chosen so that the dual-norm
+// error of the self blocks stays well below the tolerance on strongly
+// curved mixed-degree surfaces as well as on the spheres.
+constexpr int kSelfNr[9] = {10, 10, 10, 10, 14, 16, 18, 18, 20};
+constexpr int kSelfNa[9] = {16, 16, 16, 16, 20, 24, 28, 28, 32};
+
+void set_self_rule(const nfq_ctx *ctx, const nfq_params *prm, int d, QuadArgs &qa)
+{
+    qa.nr = prm->self_nr > 0 ? prm->self_nr : kSelfNr[d];
+    qa.na = prm->self_na > 0 ? prm->self_na : kSelfNa[d];
+    qa.glr = ctx->dgl + gl_offset(qa.nr);
+    qa.gla = ctx->dgl + gl_offset(qa.na);
 }
 
 }  // namespace
@@ -333,7 +347,7 @@ nfq_status ensure_self_rule(nfq_ctx *ctx, int nr, int na)
 // Builder, patch preparation and kernel arguments shared by generate and
 // adjoint.  col may be null (no column indices written).
 static nfq_status prepare(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *prm, int32_t *col,
-                   void *val, Timer &tm, bool per_pair, int nr, int na, QuadArgs &qa, PatchArgs &pa)
+                   void *val, Timer &tm, bool per_pair, QuadArgs &qa, PatchArgs &pa)
 {
     nfq_ctx *ctx = pl->ctx;
     hipStream_t st = ctx->stream;
@@ -367,26 +381,24 @@ static nfq_status prepare(nfq_plan *pl, const nfq_kernel *kern, const nfq_params
     DegTab tab = make_tab(ctx);
     tm.begin(kPhPrep, 0, st);
     hipLaunchKernelGGL(k_prep, dim3(nblk(pb.P, 64)), dim3(64), 0, st, pb, tab,
-                       prm->loosen * prm->tol, pl->coef, pl->tau, pl->flags);
+                       prm->loosen * prm->tol, pl->coef, pl->tau, pl->rho, pl->flags);
     tm.end(kPhPrep, 0, st);
     // quadratures and weights, per degree
     qa.pb = pb;
     qa.tab = tab;
-    qa.kern = Kern{kern->alpha_re, kern->alpha_im, kern->beta_re, kern->beta_im, kern->k_re, kern->k_im};
+    qa.kern = Kern{kern->alpha_re, kern->alpha_im, kern->beta_re, kern->beta_im, kern->k_re, kern->k_im,
+                   std::hypot(kern->beta_re, kern->beta_im)};
     qa.helm = (kern->k_re != 0.0 || kern->k_im != 0.0) ? 1 : 0;
     qa.max_depth = prm->max_depth;
     qa.min_depth = prm->min_depth;
     qa.rule = ctx->drule;
-    qa.glr = ctx->dglr;
-    qa.gla = ctx->dgla;
-    qa.nr = nr;
-    qa.na = na;
     qa.grp = pl->grp;
     qa.pair_tgt = pl->pair_tgt;
     qa.pair_patch = pl->pair_patch;
     qa.pair_off = pl->pair_off;
     qa.coef = pl->coef;
     qa.tau = pl->tau;
+    qa.rho = pl->rho;
     qa.val = (double *)val;
     qa.stack = pl->stack;
     qa.flags = pl->flags;
@@ -417,6 +429,7 @@ static nfq_status prepare(nfq_plan *pl, const nfq_kernel *kern, const nfq_params
         pa.pair_off = pl->pair_off;
         pa.coef = pl->coef;
         pa.tau = pl->tau;
+        pa.rho = pl->rho;
         pa.val = (double *)val;
         pa.mom = pl->mom;
         pa.mom_slot = pl->mom_slot;
@@ -465,7 +478,7 @@ nfq_status nfq_create(int device, void *hip_stream, nfq_ctx **out)
     e = dalloc(&ctx->drule, rule.size());
     if (e == hipSuccess) e = hipMemcpy(ctx->drule, rule.data(), rule.size() * 8, hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(NFQ_ERR_HIP, std::string("rule upload: ") + hipGetErrorString(e));
-    if (ensure_self_rule(ctx, 10, 16) != NFQ_OK) return bail(NFQ_ERR_HIP, "self rule upload: " + ctx->err);
+    if (upload_gauss_rules(ctx) != NFQ_OK) return bail(NFQ_ERR_HIP, "rule upload: " + ctx->err);
     *out = ctx;
     return NFQ_OK;
 }
@@ -481,8 +494,7 @@ void nfq_destroy(nfq_ctx *ctx)
         if (ctx->dD[d]) (void)hipFree(ctx->dD[d]);
     }
     if (ctx->drule) (void)hipFree(ctx->drule);
-    if (ctx->dglr) (void)hipFree(ctx->dglr);
-    if (ctx->dgla) (void)hipFree(ctx->dgla);
+    if (ctx->dgl) (void)hipFree(ctx->dgl);
     delete ctx;
 }
 
@@ -516,7 +528,7 @@ void nfq_plan_destroy(nfq_plan *pl)
     if (!pl) return;
     (void)hipSetDevice(pl->ctx->device);
     void *ptrs[] = {pl->rowlen, pl->npair, pl->pair_ptr, pl->pair_tgt, pl->pair_patch, pl->pair_self,
-                    pl->pair_off, pl->grp, pl->seg_start, pl->cursor, pl->coef, pl->tau, pl->stack,
+                    pl->pair_off, pl->grp, pl->seg_start, pl->cursor, pl->coef, pl->tau, pl->rho, pl->stack,
                     pl->flags, pl->stats, pl->counts};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -524,7 +536,7 @@ void nfq_plan_destroy(nfq_plan *pl)
         if (p) (void)hipFree(p);
     for (int64_t *p : pl->scan_tmp_p)
         if (p) (void)hipFree(p);
-    void *ptrs2[] = {pl->pcount, pl->nchunk, pl->pptr, pl->cptr, pl->pcursor, pl->plist, pl->items,
+    void *ptrs2[] = {pl->pcount, pl->nchunk, pl->pptr, pl->cptr, pl->pcursor, pl->plist, pl->plist_raw, pl->items,
                      pl->item_start, pl->item_cursor, pl->mom, pl->scoef, pl->gc_item, pl->t_pair,
                      pl->gc_self, pl->self_mark};
     for (void *p : ptrs2)
@@ -640,6 +652,7 @@ nfq_status nfq_plan_create(nfq_ctx *ctx, const nfq_surface *surf, const nfq_targ
     PL_TRY(hipMemcpy(pl->seg_start, pl->seg_start_h, sizeof(pl->seg_start_h), hipMemcpyHostToDevice));
     PL_TRY(dalloc(&pl->coef, 3 * pb.N));
     PL_TRY(dalloc(&pl->tau, pb.P));
+    PL_TRY(dalloc(&pl->rho, pb.P));
     // patch-major work items of the near kernel: sized here, built in generate
     {
         const int64_t P = pb.P;
@@ -653,6 +666,7 @@ nfq_status nfq_plan_create(nfq_ctx *ctx, const nfq_surface *surf, const nfq_targ
         PL_TRY(alloc_scan_tmp(P, pl->scan_tmp_p));
         for (int d = 1; d <= 8; ++d) pl->n_near += pl->count_h[d];
         PL_TRY(dalloc(&pl->plist, pl->n_near));
+        PL_TRY(dalloc(&pl->plist_raw, pl->n_near));
         if (NT > 0)
             hipLaunchKernelGGL(k_pairs, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, row_ptr,
                                pl->pair_ptr, pl->pair_tgt, pl->pair_patch, pl->pair_self,
@@ -703,13 +717,10 @@ nfq_status nfq_generate(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *
         prm->min_depth < 0 || prm->min_depth > prm->max_depth)
         return fail(ctx, NFQ_ERR_INVALID_ARG, "tol, loosen must be > 0; 0 <= min_depth <= max_depth <= 32");
     if (prm->ng != 0 && prm->ng != kNG) return fail(ctx, NFQ_ERR_UNSUPPORTED, "only ng = 8 is supported");
-    const int nr = prm->self_nr > 0 ? prm->self_nr : 10;
-    const int na = prm->self_na > 0 ? prm->self_na : 16;
-    if (nr > 64 || na > 64) return fail(ctx, NFQ_ERR_INVALID_ARG, "self rule sizes must be <= 64");
+    if (prm->self_nr < 0 || prm->self_na < 0 || prm->self_nr > kMaxGL || prm->self_na > kMaxGL)
+        return fail(ctx, NFQ_ERR_INVALID_ARG, "self rule sizes must be in 0..64");
     if (kern->k_im < 0.0) return fail(ctx, NFQ_ERR_INVALID_ARG, "Im k must be >= 0");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    nfq_status s0 = ensure_self_rule(ctx, nr, na);
-    if (s0 != NFQ_OK) return s0;
     hipStream_t st = ctx->stream;
     const Problem &pb = pl->pb;
     const int64_t NT = pb.NT;
@@ -724,12 +735,13 @@ nfq_status nfq_generate(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *
     const bool per_pair = (prm->flags & NFQ_FLAG_PER_PAIR) != 0;
     QuadArgs qa{};
     PatchArgs pa{};
-    nfq_status sp = prepare(pl, kern, prm, col, val, tm, per_pair, nr, na, qa, pa);
+    nfq_status sp = prepare(pl, kern, prm, col, val, tm, per_pair, qa, pa);
     if (sp != NFQ_OK) return sp;
     for (int d = 1; d <= 8; ++d) {
         const int64_t ns = pl->seg_start_h[d], nc = pl->seg_len_h[d];
         const int64_t ss = pl->seg_start_h[9 + d], sc = pl->seg_len_h[9 + d];
         if (nc + sc == 0) continue;
+        set_self_rule(ctx, prm, d, qa);
         if (cplx) launch_degree<true>(d, pl, qa, ns, nc, ss, sc, st, tm, per_pair, pa);
         else launch_degree<false>(d, pl, qa, ns, nc, ss, sc, st, tm, per_pair, pa);
     }
@@ -788,13 +800,10 @@ nfq_status nfq_adjoint(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *p
         prm->min_depth < 0 || prm->min_depth > prm->max_depth)
         return fail(ctx, NFQ_ERR_INVALID_ARG, "tol, loosen must be > 0; 0 <= min_depth <= max_depth <= 32");
     if (prm->ng != 0 && prm->ng != kNG) return fail(ctx, NFQ_ERR_UNSUPPORTED, "only ng = 8 is supported");
-    const int nr = prm->self_nr > 0 ? prm->self_nr : 10;
-    const int na = prm->self_na > 0 ? prm->self_na : 16;
-    if (nr > 64 || na > 64) return fail(ctx, NFQ_ERR_INVALID_ARG, "self rule sizes must be <= 64");
+    if (prm->self_nr < 0 || prm->self_na < 0 || prm->self_nr > kMaxGL || prm->self_na > kMaxGL)
+        return fail(ctx, NFQ_ERR_INVALID_ARG, "self rule sizes must be in 0..64");
     if (kern->k_im < 0.0) return fail(ctx, NFQ_ERR_INVALID_ARG, "Im k must be >= 0");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    nfq_status s0 = ensure_self_rule(ctx, nr, na);
-    if (s0 != NFQ_OK) return s0;
     hipStream_t st = ctx->stream;
     const Problem &pb = pl->pb;
     const int64_t N = pb.N, NT = pb.NT;
@@ -816,7 +825,7 @@ nfq_status nfq_adjoint(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *p
     Timer tm{pl, false};
     QuadArgs qa{};
     PatchArgs pa{};
-    nfq_status sp = prepare(pl, kern, prm, nullptr, nullptr, tm, false, nr, na, qa, pa);
+    nfq_status sp = prepare(pl, kern, prm, nullptr, nullptr, tm, false, qa, pa);
     if (sp != NFQ_OK) return sp;
     DegTab tab = make_tab(ctx);
     HIP_TRY(ctx, hipMemsetAsync(pl->self_mark, 0, N * sizeof(unsigned int), st));
@@ -841,6 +850,7 @@ nfq_status nfq_adjoint(nfq_plan *pl, const nfq_kernel *kern, const nfq_params *p
     for (int d = 1; d <= 8; ++d) {
         const int64_t ss = pl->seg_start_h[9 + d], sc = pl->seg_len_h[9 + d];
         AdjArgs ad = aa;
+        set_self_rule(ctx, prm, d, ad.qa);
         if (sc > 0) {
             ad.qa.seg = ss;
             ad.qa.count = sc;

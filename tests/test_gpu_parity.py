@@ -76,14 +76,8 @@ def _check_against_golden(name, prob, rp, val, factor=10.0):
     return worst, n
 
 
-MIXED_SKIP = ("mixed-degree fixture ran past the GPU silence limit twice; kept off the GPU "
-              "until the cause is shown on the CPU")
-
-
 @pytest.mark.parametrize("name", ["laplace_s_sphere80_d3", "cfie_sphere1280_d4",
-                                  "cfie_sphere320_d4_k5",
-                                  pytest.param("mixed_small_d1to8",
-                                               marks=pytest.mark.skip(reason=MIXED_SKIP))])
+                                  "cfie_sphere320_d4_k5", "mixed_small_d1to8"])
 def test_parity_against_oracle(ctx, name):
     from paper_2006_02545_amd import nfq
     print("parity case", name, flush=True)
@@ -96,7 +90,6 @@ def test_parity_against_oracle(ctx, name):
     print("worst dual-norm error / eps = %.3g over %d blocks; stats %s" % (worst, n, st))
 
 
-@pytest.mark.skip(reason=MIXED_SKIP)
 def test_structure_and_determinism(ctx):
     """Row pointers and columns bit-exact; two runs bitwise identical."""
     from paper_2006_02545_amd import nfq
