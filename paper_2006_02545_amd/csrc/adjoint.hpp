@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
 {
     using S = PatchShape<D, true>;
     constexpr int ND = S::ND, W = S::W, PL = S::PL, G0 = S::G0, KS = S::KS, R = S::R;
-    constexpr int GSA = (KS + 8 + 6) | 1;   // forward row + X_u, X_v
+    constexpr int GSA = (KS + 7 + 6) | 1;   // forward row + X_u, X_v
     const PatchArgs &a = aa.pa;
     __shared__ double s_geo[256 * GSA];
     __shared__ GroupEntry s_stack[kGroupStack];
@@ -246,6 +246,7 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
     __shared__ double s_cf[3 * ND];
     __shared__ double s_cm[4 * W];
     __shared__ double s_g2[4];
+    __shared__ double s_nf[64];
     __shared__ unsigned long long s_fail;
     __shared__ int s_sp;
 
@@ -265,10 +266,6 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
         const double *cf = s_cf;
         const double tau = a.tau[j];
         const double rho_j = a.rho[j];
-        auto nfac = [&](int s) {
-            return noise_factor(__builtin_sqrt(s_x[s][0] * s_x[s][0] + s_x[s][1] * s_x[s][1] +
-                                               s_x[s][2] * s_x[s][2]) + rho_j);
-        };
         unsigned item_groups = 0;
         if (tid < count) {
             const int p = a.plist[start + tid];
@@ -276,6 +273,9 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
             s_x[tid][0] = a.pb.txyz[3 * t];
             s_x[tid][1] = a.pb.txyz[3 * t + 1];
             s_x[tid][2] = a.pb.txyz[3 * t + 2];
+            // rounding-floor factor of this target (see kNoiseKappa)
+            s_nf[tid] = noise_factor(__builtin_sqrt(s_x[tid][0] * s_x[tid][0] + s_x[tid][1] * s_x[tid][1] +
+                                                    s_x[tid][2] * s_x[tid][2]) + rho_j);
             s_lam[tid][0] = aa.lam[2 * t];
             s_lam[tid][1] = -aa.lam[2 * t + 1];  // conj(lambda)
             s_pair[tid] = p;
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
             for (int v = 0; v < W; ++v) acc[v] = 0.0;
             const double *g = s_geo + lane * GSA;
             double fr, fi, sn;
-            kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular, sn);
+            kern_node(a.kern, a.helm, x, g + G0, g[pad_slot<S::R>(l16)], fr, fi, singular, sn);
             mac_node<D, true>(acc, g, fr, fi);
             rot_reduce16<PL>(acc);
 #pragma unroll
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                 {
                     const double *g = s_geo + tid * GSA;
                     double fr, fi;
-                    kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular, sens);
+                    kern_node(a.kern, a.helm, x, g + G0, g[pad_slot<S::R>(l16)], fr, fi, singular, sens);
                     mac_node<D, true>(acc, g, fr, fi);
                 }
                 sens = wave_total(sens);
@@ -390,10 +390,10 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                     const int o = PL * l16 + i;
                     const double v = (s_cm[o] + s_cm[W + o]) + (s_cm[2 * W + o] + s_cm[3 * W + o]);
                     const double df = v - IT[i];
-                    e2 = __builtin_fma(df, df, e2);
+                    if (PL * l16 + i < S::NV) e2 = __builtin_fma(df, df, e2);
                 }
                 const double err2 = lane0(row_sum16(e2));
-                const double noise2 = nfac(s) * ((s_g2[0] + s_g2[1]) + (s_g2[2] + s_g2[3]));
+                const double noise2 = s_nf[s] * ((s_g2[0] + s_g2[1]) + (s_g2[2] + s_g2[3]));
                 bool accept = (err2 <= thr * thr || err2 <= noise2) && L + 1 >= a.min_depth;
                 if (!accept && (L + 1 >= a.max_depth || capped)) accept = true;
                 if (!accept) {
@@ -426,11 +426,10 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                     for (int i = 0; i < 4; ++i) {
                         const double *g = s_geo + (grp16 * 64 + l16 + 16 * i) * GSA;
                         double fr, fi, sn;
-                        kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular, sn);
+                        kern_node(a.kern, a.helm, x, g + G0, g[pad_slot<S::R>(l16)], fr, fi, singular, sn);
                         mac_node<D, true>(acc, g, fr, fi);
                         sens += sn;
                     }
-                    const double noise2 = nfac(s) * wave_total(sens);
                     rot_reduce16<PL>(acc);
                     double e2 = 0.0;
 #pragma unroll
@@ -438,10 +437,11 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
                         double v = acc[i] + __shfl_xor(acc[i], 16, 64);
                         v += __shfl_xor(v, 32, 64);
                         const double df = v - IT[i];
-                        e2 = __builtin_fma(df, df, e2);
+                        if (PL * l16 + i < S::NV) e2 = __builtin_fma(df, df, e2);
                     }
                     const double err2 = lane0(row_sum16(e2));
-                    bool accept = (err2 <= thr * thr || err2 <= noise2) && L + 1 >= a.min_depth;
+                    bool accept = (err2 <= thr * thr || err2 <= s_nf[s] * wave_total(sens)) &&
+                                  L + 1 >= a.min_depth;
                     if (!accept && (L + 1 >= a.max_depth || capped)) accept = true;
                     if (!accept) {
                         double *dst = mptr(L + 1, grp16, s);
@@ -457,8 +457,8 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
             if (accm != 0ull) {
                 const double *g = s_geo + tid * GSA;
                 const double X[3] = {g[G0], g[G0 + 1], g[G0 + 2]};
-                const double Xu[3] = {g[G0 + 8], g[G0 + 9], g[G0 + 10]};
-                const double Xv[3] = {g[G0 + 11], g[G0 + 12], g[G0 + 13]};
+                const double Xu[3] = {g[G0 + 7], g[G0 + 8], g[G0 + 9]};
+                const double Xv[3] = {g[G0 + 10], g[G0 + 11], g[G0 + 12]};
                 const double n[3] = {Xu[1] * Xv[2] - Xu[2] * Xv[1], Xu[2] * Xv[0] - Xu[0] * Xv[2],
                                      Xu[0] * Xv[1] - Xu[1] * Xv[0]};
                 const double wq = a.rule[3 * (tid & 63) + 2] * area;

@@ -41,12 +41,22 @@ struct PatchShape {
     static constexpr int KS = 16 * R;                // basis slots per node
     static constexpr int PL = R * C;                 // doubles per lane after the reduce-scatter
     static constexpr int W = 16 * PL;                // doubles per lane before it
-    static constexpr int GS = (KS + 8) | 1;          // LDS doubles per node (odd pitch)
-    static constexpr int G0 = KS;                    // y, n w, J w, |K|^2 follow the basis slots
+    static constexpr int GS = (KS + 7) | 1;          // LDS doubles per node (odd pitch)
+    static constexpr int G0 = KS;                    // y, n w, J w follow the basis slots
+    // The last basis slot (index KS - 1 >= ND) is padding; it carries |K|^2
+    // of the node instead of zero.  The moment component it feeds (>= NV) is
+    // kept out of the test and of the output.
     // per-target totals kept in LDS when they fit beside the geometry
     static constexpr bool TOT_LDS = (64 * NV + 256 * GS) * 8 <= 140 * 1024;
     static constexpr int TOTN = TOT_LDS ? 64 * NV : 1;
 };
+
+// Rotated position of the padding slot for reader row lane l16.
+template <int R>
+__device__ __forceinline__ int pad_slot(int l16)
+{
+    return ((15 - l16) & 15) * R + R - 1;
+}
 
 // Doubles per lane of the moment vectors for degree d (host sizing).
 inline constexpr int patch_w(int d, bool cplx)
@@ -146,11 +156,10 @@ __device__ __forceinline__ void node_geometry(const double *cf, double Ax, doubl
     double kk2 = 0.0;
 #pragma unroll
     for (int m = 0; m < ND; ++m) kk2 = __builtin_fma(K[m], K[m], kk2);
-    g[G0 + 7] = kk2;
     if (DERIV) {
         // chart derivatives for the adjoint
-        g[G0 + 8] = Xu[0]; g[G0 + 9] = Xu[1]; g[G0 + 10] = Xu[2];
-        g[G0 + 11] = Xv[0]; g[G0 + 12] = Xv[1]; g[G0 + 13] = Xv[2];
+        g[G0 + 7] = Xu[0]; g[G0 + 8] = Xu[1]; g[G0 + 9] = Xu[2];
+        g[G0 + 10] = Xv[0]; g[G0 + 11] = Xv[1]; g[G0 + 12] = Xv[2];
     }
     int rot = (16 - l16) & 15;
     // keep the slot addresses local to this call (hoisting them out of the
@@ -159,7 +168,7 @@ __device__ __forceinline__ void node_geometry(const double *cf, double Ax, doubl
 #pragma unroll
     for (int m = 0; m < 16 * R; ++m) {
         const int unit = m / R, r = m - unit * R;
-        g[((unit + rot) & 15) * R + r] = m < ND ? K[m] : 0.0;
+        g[((unit + rot) & 15) * R + r] = m < ND ? K[m] : (m == 16 * R - 1 ? kk2 : 0.0);
     }
 }
 
@@ -182,10 +191,10 @@ __device__ __forceinline__ void mac_node(double *acc, const double *g, double fr
 
 // Weighted kernel value at a node whose geometry g carries n w and J w.
 __device__ __forceinline__ void kern_node(const Kern &k, bool helm, const double x[3],
-                                          const double *g, double &fr, double &fi, int &singular,
-                                          double &sens)
+                                          const double *g, double kk2, double &fr, double &fi,
+                                          int &singular, double &sens)
 {
-    // g points at the node's y, n w, J w, |K|^2; sens: rounding sensitivity
+    // g points at the node's y, n w, J w; sens: rounding sensitivity
     // (|f|^2 / r^2 + b^2) |K|^2 of the weighted value (see kNoiseKappa)
     const double dx = x[0] - g[0], dy = x[1] - g[1], dz = x[2] - g[2];
     const double r2 = dx * dx + dy * dy + dz * dz;
@@ -199,7 +208,7 @@ __device__ __forceinline__ void kern_node(const Kern &k, bool helm, const double
     if (!helm) {
         fr = k.ar * gJ + k.br * d0;
         fi = k.ai * gJ + k.bi * d0;
-        sens = ((fr * fr + fi * fi) * rinv2 + bs * bs) * g[7];
+        sens = ((fr * fr + fi * fi) * rinv2 + bs * bs) * kk2;
         return;
     }
     const double r = r2 * rinv;
@@ -215,7 +224,7 @@ __device__ __forceinline__ void kern_node(const Kern &k, bool helm, const double
     const double qr = d0 * (pr * c - pi * s), qi = d0 * (pr * s + pi * c);
     fr = k.ar * gr - k.ai * gi + k.br * qr - k.bi * qi;
     fi = k.ar * gi + k.ai * gr + k.br * qi + k.bi * qr;
-    sens = ((fr * fr + fi * fi) * rinv2 + bs * bs) * g[7];
+    sens = ((fr * fr + fi * fi) * rinv2 + bs * bs) * kk2;
 }
 
 // Sum over the wavefront, into every lane (row sums by rotation, then the
@@ -254,6 +263,7 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
     __shared__ double s_cf[3 * S::ND];
     __shared__ double s_cm[4 * W];
     __shared__ double s_g2[4];
+    __shared__ double s_nf[64];
     __shared__ unsigned long long s_fail;
     __shared__ int s_sp;
 
@@ -275,10 +285,6 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
         const double tau = a.tau[j];
         const double rho_j = a.rho[j];
         // rounding-floor factor of target s (see kNoiseKappa)
-        auto nfac = [&](int s) {
-            return noise_factor(__builtin_sqrt(s_x[s][0] * s_x[s][0] + s_x[s][1] * s_x[s][1] +
-                                               s_x[s][2] * s_x[s][2]) + rho_j);
-        };
         unsigned item_groups = 0;
         if (tid < count) {
             const int p = a.plist[start + tid];
@@ -286,6 +292,9 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
             s_x[tid][0] = a.pb.txyz[3 * t];
             s_x[tid][1] = a.pb.txyz[3 * t + 1];
             s_x[tid][2] = a.pb.txyz[3 * t + 2];
+            // rounding-floor factor of this target (see kNoiseKappa)
+            s_nf[tid] = noise_factor(__builtin_sqrt(s_x[tid][0] * s_x[tid][0] + s_x[tid][1] * s_x[tid][1] +
+                                                    s_x[tid][2] * s_x[tid][2]) + rho_j);
             const int64_t off = a.pair_off[p];
             s_off[tid] = off;
             if (!S::TOT_LDS)
@@ -308,7 +317,7 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
             for (int v = 0; v < W; ++v) acc[v] = 0.0;
             const double *g = s_geo + lane * GS;
             double fr, fi, sn;
-            kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular, sn);
+            kern_node(a.kern, a.helm, x, g + G0, g[pad_slot<S::R>(l16)], fr, fi, singular, sn);
             mac_node<D, CPLX>(acc, g, fr, fi);
             rot_reduce16<PL>(acc);
 #pragma unroll
@@ -385,7 +394,7 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                 {
                     const double *g = s_geo + tid * GS;
                     double fr, fi;
-                    kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular, sens);
+                    kern_node(a.kern, a.helm, x, g + G0, g[pad_slot<S::R>(l16)], fr, fi, singular, sens);
                     mac_node<D, CPLX>(acc, g, fr, fi);
                 }
                 sens = wave_total(sens);
@@ -408,10 +417,10 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                     const double v = (s_cm[o] + s_cm[W + o]) + (s_cm[2 * W + o] + s_cm[3 * W + o]);
                     Ssum[i] = v;
                     const double df = v - IT[i];
-                    e2 = __builtin_fma(df, df, e2);
+                    if (PL * l16 + i < S::NV) e2 = __builtin_fma(df, df, e2);
                 }
                 const double err2 = lane0(row_sum16(e2));
-                const double noise2 = nfac(s) * ((s_g2[0] + s_g2[1]) + (s_g2[2] + s_g2[3]));
+                const double noise2 = s_nf[s] * ((s_g2[0] + s_g2[1]) + (s_g2[2] + s_g2[3]));
                 if (mine) {
                     ++st_checks;
                     st_visits += 4;
@@ -464,11 +473,10 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                     for (int i = 0; i < 4; ++i) {
                         const double *g = s_geo + (grp16 * 64 + l16 + 16 * i) * GS;
                         double fr, fi, sn;
-                        kern_node(a.kern, a.helm, x, g + G0, fr, fi, singular, sn);
+                        kern_node(a.kern, a.helm, x, g + G0, g[pad_slot<S::R>(l16)], fr, fi, singular, sn);
                         mac_node<D, CPLX>(acc, g, fr, fi);
                         sens += sn;
                     }
-                    const double noise2 = nfac(s) * wave_total(sens);
                     rot_reduce16<PL>(acc);
                     // acc[0..PL): unit l16 of child grp16's moments; the sum over
                     // the four children by two more exchanges
@@ -480,13 +488,14 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                         v += __shfl_xor(v, 32, 64);
                         Ssum[i] = v;
                         const double df = v - IT[i];
-                        e2 = __builtin_fma(df, df, e2);
+                        if (PL * l16 + i < S::NV) e2 = __builtin_fma(df, df, e2);
                     }
                     // every row holds the same children sum: row 0's total decides
                     const double err2 = lane0(row_sum16(e2));
                     ++st_checks;
                     st_visits += 4;
-                    const bool ok = err2 <= thr * thr || err2 <= noise2;
+                    // the rounding floor is summed only when the threshold fails
+                    const bool ok = err2 <= thr * thr || err2 <= s_nf[s] * wave_total(sens);
                     bool accept = ok && L + 1 >= a.min_depth;
                     if (!accept && (L + 1 >= a.max_depth || capped)) {
                         accept = true;
