@@ -576,7 +576,32 @@ struct SelfShape {
     static constexpr int NV = CPLX ? 2 * ND : ND;
     static constexpr int RP = (ND + 2) | 1;   // LDS row pitch: K[ND], f_re w, f_im w
     static constexpr int WPB = 2;
+    // small moment vectors are accumulated per lane in registers and reduced
+    // once per target; large ones are staged through LDS every 64 nodes
+    static constexpr int W = (NV + 15) / 16 * 16;
+    static constexpr bool REG = W <= 32;
 };
+
+// 16-lane reduce-scatter: on entry acc[W] holds this lane's partial sums;
+// on exit acc[0..W/16) holds components [W/16 (lane & 15), W/16 (lane & 15)
+// + W/16) summed over the 16 lanes of the lane's row.
+template <int W>
+__device__ __forceinline__ void reduce_scatter_rows(double *acc, int lane)
+{
+#pragma unroll
+    for (int step = 0; step < 4; ++step) {
+        const int m = 8 >> step;
+        const int w = W >> (step + 1);
+        const bool hi = (lane & m) != 0;
+#pragma unroll
+        for (int i = 0; i < w; ++i) {
+            const double lo_v = acc[i], hi_v = acc[i + w];
+            const double send = hi ? lo_v : hi_v;
+            const double keep = hi ? hi_v : lo_v;
+            acc[i] = keep + __shfl_xor(send, m, 64);
+        }
+    }
+}
 
 // Self quadrature.  One wavefront per target; the target-split rule's nodes
 // are taken 64 at a time (one per lane): each lane evaluates chart, kernel and
@@ -592,6 +617,7 @@ __global__ __launch_bounds__((64 * SelfShape<D, CPLX>::WPB)) void k_self(QuadArg
     __shared__ double s_stage[WPB][64 * RP];
     // per wavefront: up to 6 panels x (A, E, mu, h/L, det, xi_a, xi_b)
     __shared__ double s_pan[WPB][6][kPanW];
+    __shared__ double s_cfw[WPB][3 * ND];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double *stage = s_stage[wv];
     const int64_t wave_id = (int64_t)blockIdx.x * WPB + wv;
@@ -606,7 +632,12 @@ __global__ __launch_bounds__((64 * SelfShape<D, CPLX>::WPB)) void k_self(QuadArg
         const int j = __builtin_amdgcn_readfirstlane(a.pair_patch[p]);
         const int64_t nb = a.pb.node_ptr[j];
         const int l = (int)(a.pb.node_of_target[t] - nb);
-        const double *cf = a.coef + 3 * nb;
+        // chart coefficients in LDS, read at every node (kept out of registers)
+        for (int k = lane; k < 3 * ND; k += 64) s_cfw[wv][k] = a.coef[3 * nb + k];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double *cf = s_cfw[wv];
         const double tu = a.tab.uv[D][2 * l], tv = a.tab.uv[D][2 * l + 1];
         ++st_pairs;
         // target = chart point X(t); first fundamental form at t
@@ -655,11 +686,70 @@ __global__ __launch_bounds__((64 * SelfShape<D, CPLX>::WPB)) void k_self(QuadArg
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int per_panel = na * nr;
+        const int total = npan * per_panel;
+        // node q -> panel, angular, radial index (float reciprocals: exact
+        // for these small integers)
+        const float inv_pp = 1.0f / (float)per_panel, inv_nr = 1.0f / (float)nr;
+        if constexpr (S::REG) {
+            constexpr int W = S::W, PL = W / 16;
+            double racc[W];
+#pragma unroll
+            for (int v = 0; v < W; ++v) racc[v] = 0.0;
+            for (int q = lane; q < total; q += 64) {
+                const int pi = (int)(((float)q + 0.5f) * inv_pp);
+                const int rem = q - pi * per_panel;
+                const int ia = (int)(((float)rem + 0.5f) * inv_nr), ir = rem - ia * nr;
+                const double *pp = s_pan[wv][pi];
+                const double Ax = pp[0], Ay = pp[1], Ex = pp[2], Ey = pp[3], mu = pp[4];
+                const double hl = pp[5], det = pp[6], xa = pp[7], xb = pp[8];
+                const double xi = xa + (xb - xa) * a.gla[2 * ia];
+                // sinh and cosh from one exponential (lam needs absolute accuracy)
+                const double ex = exp(xi), exi = 1.0 / ex;
+                const double lam = mu + hl * (0.5 * (ex - exi));
+                const double dlam = hl * (0.5 * (ex + exi)) * (xb - xa) * a.gla[2 * ia + 1];
+                const double s = a.glr[2 * ir], ws = a.glr[2 * ir + 1];
+                const double dx = Ax + lam * Ex - tu, dy = Ay + lam * Ey - tv;
+                double K[ND], X[3], Xu[3], Xv[3];
+                const double *cfn = cf;
+                asm volatile("" : "+v"(cfn));
+                chart_eval<D>(cfn, tu + s * dx, tv + s * dy, K, X, Xu, Xv);
+                const double n[3] = {Xu[1] * Xv[2] - Xu[2] * Xv[1], Xu[2] * Xv[0] - Xu[0] * Xv[2],
+                                     Xu[0] * Xv[1] - Xu[1] * Xv[0]};
+                double fr, fi;
+                kern_eval(a.kern, a.helm, x, X, n, fr, fi, singular);
+                const double w = s * det * ws * dlam;
+                fr *= w;
+                fi *= w;
+#pragma unroll
+                for (int m = 0; m < ND; ++m) {
+                    if (CPLX) {
+                        racc[2 * m] = __builtin_fma(fr, K[m], racc[2 * m]);
+                        racc[2 * m + 1] = __builtin_fma(fi, K[m], racc[2 * m + 1]);
+                    } else {
+                        racc[m] = __builtin_fma(fr, K[m], racc[m]);
+                    }
+                }
+            }
+            reduce_scatter_rows<W>(racc, lane);
+#pragma unroll
+            for (int i = 0; i < PL; ++i) {
+                racc[i] += __shfl_xor(racc[i], 16, 64);
+                racc[i] += __shfl_xor(racc[i], 32, 64);
+            }
+            if (lane < 16) {
+                const int64_t off = a.pair_off[p];
+#pragma unroll
+                for (int i = 0; i < PL; ++i) {
+                    const int v = PL * lane + i;
+                    if (v < NV) a.val[(CPLX ? 2 : 1) * off + v] = racc[i];
+                }
+            }
+            continue;
+        }
         double acc[NL];
 #pragma unroll
         for (int k = 0; k < NL; ++k) acc[k] = 0.0;
-        const int per_panel = na * nr;
-        const int total = npan * per_panel;
         for (int base = 0; base < total; base += 64) {
             const int q = base + lane;
             double fr = 0.0, fi = 0.0;
@@ -667,9 +757,9 @@ __global__ __launch_bounds__((64 * SelfShape<D, CPLX>::WPB)) void k_self(QuadArg
 #pragma unroll
             for (int m = 0; m < ND; ++m) K[m] = 0.0;
             if (q < total) {
-                const int pi = q / per_panel;
+                const int pi = (int)(((float)q + 0.5f) * inv_pp);
                 const int rem = q - pi * per_panel;
-                const int ia = rem / nr, ir = rem - ia * nr;
+                const int ia = (int)(((float)rem + 0.5f) * inv_nr), ir = rem - ia * nr;
                 const double *pp = s_pan[wv][pi];
                 const double Ax = pp[0], Ay = pp[1], Ex = pp[2], Ey = pp[3], mu = pp[4];
                 const double hl = pp[5], det = pp[6], xa = pp[7], xb = pp[8];
