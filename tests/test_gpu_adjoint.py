@@ -10,6 +10,9 @@ the C ABI.
   zero and its moment sum_n x_n x dPhi/dx_n vanishes.
 * Phi is linear in alpha and beta: dPhi/dalpha and dPhi/dbeta are the
   single- and double-layer values of Phi.
+* Against the oracle: central differences of the oracle's own Phi (method
+  mode, uniform depth-2 trees) for off-surface targets, i.e. the near part of
+  the gradient with respect to patch nodes and the wavenumber.
 """
 import numpy as np
 import pytest
@@ -89,3 +92,62 @@ def test_adjoint_invariances_and_linearity(ctx):
     # (the forward with alpha = 1, beta = 0 takes its own adaptive decisions: agreement to ~eps)
     assert abs(da - phiS) <= 1e-7 * abs(phiS), (da, phiS)
     assert abs(db - phiD) <= 1e-7 * abs(phiD), (db, phiD)
+
+
+def _offsurface_problem():
+    """Degree-3 sphere (80 patches) with 40 targets 5 % outside the surface
+    and their near lists (|x - c_j| < eta R_j)."""
+    from paper_2006_02545_amd import surfaces as S
+    prob = S.sphere_problem(1, 3, -3j, 1.0, 3.0, 1e-8, seed=2, density="gauss")
+    rng = np.random.default_rng(11)
+    pick = rng.choice(prob.NT, 40, replace=False)
+    xt = prob.target_xyz[pick] * 1.05
+    rows = [np.nonzero(np.linalg.norm(xt[i] - prob.centers, axis=1) < prob.eta * prob.radii)[0]
+            for i in range(len(xt))]
+    prob.target_xyz = xt
+    prob.node_of_target = np.full(len(xt), -1, dtype=np.int64)
+    prob.near_row_ptr = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    prob.near_patch = np.concatenate(rows).astype(np.int32)
+    prob.lam = prob.lam[pick]
+    return prob
+
+
+def _oracle_phi(prob, xyz, k, depth):
+    import oracle
+    from dataclasses import replace
+    p2 = replace(prob, xyz=xyz)
+    run = oracle.OracleRun(p2, mode=oracle.METHOD, tol=1e-300, max_depth=depth, k=k)
+    phi = 0j
+    for t in range(p2.NT):
+        for j in p2.near_patch[p2.near_row_ptr[t]:p2.near_row_ptr[t + 1]]:
+            a = run.pair(t, int(j))
+            sl = slice(p2.node_ptr[j], p2.node_ptr[j + 1])
+            phi += np.conj(p2.lam[t]) * np.dot(a, p2.sigma[sl])
+    return phi
+
+
+def test_adjoint_matches_oracle_gradient(ctx):
+    from paper_2006_02545_amd import nfq
+    print("adjoint oracle-gradient case sphere80_d3 off-surface depth 2", flush=True)
+    prob = _offsurface_problem()
+    depth = 2
+    plan = nfq.plan_for(ctx, prob)
+    grad, gk, _, _ = plan.adjoint(prob.alpha, prob.beta, prob.k, prob.tol, prob.sigma, prob.lam,
+                                  min_depth=depth, max_depth=depth)
+    # the same uniform quadrature on both sides: the oracle never accepts
+    # before the depth limit at tol 1e-300
+    h = 1e-5
+    rng = np.random.default_rng(3)
+    used = np.unique(np.concatenate([np.arange(prob.node_ptr[j], prob.node_ptr[j + 1])
+                                     for j in np.unique(prob.near_patch)]))
+    scale = np.abs(grad).max()
+    for n in rng.choice(used, 4, replace=False):
+        c = int(rng.integers(0, 3))
+        xp, xm = prob.xyz.copy(), prob.xyz.copy()
+        xp[n, c] += h
+        xm[n, c] -= h
+        fd = (_oracle_phi(prob, xp, prob.k, depth) - _oracle_phi(prob, xm, prob.k, depth)) / (2 * h)
+        assert abs(fd - grad[n, c]) <= 1e-6 * scale, (n, c, fd, grad[n, c], scale)
+    k = prob.k
+    fdk = (_oracle_phi(prob, prob.xyz, k + h, depth) - _oracle_phi(prob, prob.xyz, k - h, depth)) / (2 * h)
+    assert abs(fdk - gk) <= 1e-6 * max(1.0, abs(gk)), (fdk, gk)
