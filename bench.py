@@ -84,8 +84,8 @@ def cpu_baseline(seconds, workers):
 # --copy-calibration 1024: FETCH_SIZE reads 0.5 GiB, WRITE_SIZE 1 GiB), valid
 # for the kernel sources with this digest.
 TRAFFIC_RECORD = {
-    "sources_sha256": "e2d36be77cfc103cdcdd5fb37dbada58a689199bde208aacafbd777831b1c51e",
-    "fetch_kib": 158417.1, "write_kib": 361133.9,
+    "sources_sha256": "93711910743a31e07b810c7766dd89b20ebecb020297407796ee4c407de8e3b6",
+    "fetch_kib": 178196.3, "write_kib": 374789.5,
     "fetch_scale": 2.0, "write_scale": 1.0,
 }
 NEAR_SOURCES = ["near_patch.hpp", "kernels.hpp", "device.hpp", "fastmath.hpp", "koorn.hpp"]

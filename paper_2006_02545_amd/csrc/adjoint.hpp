@@ -281,6 +281,8 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
             s_pair[tid] = p;
         }
         for (int k = tid; k < 64 * 6; k += 256) (&s_t[0][0])[k] = 0.0;
+        // the chart and density coefficients were staged by every wave
+        __syncthreads();
         if (tid < 64)
             node_geometry<D, true, true>(cf, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, a.rule[3 * tid],
                                          a.rule[3 * tid + 1], a.rule[3 * tid + 2],

@@ -302,6 +302,8 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
         }
         if (S::TOT_LDS)
             for (int k = tid; k < 64 * NV; k += 256) s_tot[k] = 0.0;
+        // the chart coefficients were staged by every wave
+        __syncthreads();
         if (tid < 64) {
             // root geometry: node tid of the rule on T0, read by lane tid
             node_geometry<D, CPLX>(cf, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, a.rule[3 * tid],
