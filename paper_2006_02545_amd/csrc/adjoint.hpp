@@ -124,73 +124,6 @@ __device__ __forceinline__ void node_grad(const Kern &k, const double x[3], cons
     cmul(Wr, Wi, Fr * nr, Fi * nr, g.dr, g.di);
 }
 
-// Chart with the basis derivatives: K, Ku, Kv, X, Xu, Xv at (u,v).
-template <int D>
-__device__ __forceinline__ void chart_eval_d(const double *__restrict__ coef, double u, double v,
-                                             double *K, double *Ku, double *Kv, double X[3],
-                                             double Xu[3], double Xv[3])
-{
-    constexpr int ND = nd_of(D);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) X[c] = Xu[c] = Xv[c] = 0.0;
-    koorn_visit<D>(u, v, [&](int a, double k, double ku, double kv) {
-        K[a] = k;
-        Ku[a] = ku;
-        Kv[a] = kv;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double cf = coef[c * ND + a];
-            X[c] = __builtin_fma(cf, k, X[c]);
-            Xu[c] = __builtin_fma(cf, ku, Xu[c]);
-            Xv[c] = __builtin_fma(cf, kv, Xv[c]);
-        }
-    });
-}
-
-// Accumulate one node's contribution: GC[(c * ND + a) * 2 + {re, im}] +=
-// gX_c K_a + (Xv x gn)_c Ku_a + (gn x Xu)_c Kv_a; and the per-target sums.
-template <int ND>
-__device__ __forceinline__ void accumulate_node(const NodeGrad &g, const double *K,
-                                                const double *Ku, const double *Kv,
-                                                const double Xu[3], const double Xv[3],
-                                                double *GC, double *T12)
-{
-    // b = Xv x gn, d = gn x Xu (complex)
-    double br[3], bi[3], dr[3], di[3];
-    br[0] = Xv[1] * g.gnr[2] - Xv[2] * g.gnr[1];
-    br[1] = Xv[2] * g.gnr[0] - Xv[0] * g.gnr[2];
-    br[2] = Xv[0] * g.gnr[1] - Xv[1] * g.gnr[0];
-    bi[0] = Xv[1] * g.gni[2] - Xv[2] * g.gni[1];
-    bi[1] = Xv[2] * g.gni[0] - Xv[0] * g.gni[2];
-    bi[2] = Xv[0] * g.gni[1] - Xv[1] * g.gni[0];
-    dr[0] = g.gnr[1] * Xu[2] - g.gnr[2] * Xu[1];
-    dr[1] = g.gnr[2] * Xu[0] - g.gnr[0] * Xu[2];
-    dr[2] = g.gnr[0] * Xu[1] - g.gnr[1] * Xu[0];
-    di[0] = g.gni[1] * Xu[2] - g.gni[2] * Xu[1];
-    di[1] = g.gni[2] * Xu[0] - g.gni[0] * Xu[2];
-    di[2] = g.gni[0] * Xu[1] - g.gni[1] * Xu[0];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int a = 0; a < ND; ++a) {
-            double *p = GC + 2 * (c * ND + a);
-            p[0] += g.gXr[c] * K[a] + br[c] * Ku[a] + dr[c] * Kv[a];
-            p[1] += g.gXi[c] * K[a] + bi[c] * Ku[a] + di[c] * Kv[a];
-        }
-    // target gradient -gX, dPhi/dk, phiS, phiD
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        T12[2 * c] -= g.gXr[c];
-        T12[2 * c + 1] -= g.gXi[c];
-    }
-    T12[6] += g.gkr;
-    T12[7] += g.gki;
-    T12[8] += g.sr;
-    T12[9] += g.si;
-    T12[10] += g.dr;
-    T12[11] += g.di;
-}
-
 struct AdjArgs {
     PatchArgs pa;             // forward arguments (val unused)
     QuadArgs qa;              // self-rule arguments
@@ -598,16 +531,33 @@ __global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
 }
 
 // Self pairs: the forward's target-split rule, differentiated with the rule
-// (split points, sinh grading) held fixed.
+// (split points, sinh grading) held fixed.  One wavefront per self target.
+// The rule nodes go 64 at a time, one per lane: a lane evaluates the chart,
+// the density and the kernel derivatives at its node and leaves in LDS the
+// eighteen weighted terms f = gX, b = Xv x gn, d = gn x Xu (complex
+// 3-vectors) and the basis values K.  The moments M[f]_m = sum_q f(q) K_m(q)
+// are accumulated transposed: lane (m mod 16, g) takes basis functions
+// m mod 16 + 16 r and the nodes q = g (mod 4), and the four node classes are
+// summed at the end.  The chart-coefficient gradient then follows from the
+// basis differentiation matrices, as in the patch adjoint:
+//     GC[c][a] = M[gX_c]_a + sum_m Du[a][m] M[b_c]_m + Dv[a][m] M[d_c]_m.
+// The LDS footprint (K rows only) leaves room for two wavefronts per SIMD.
 template <int D>
 __global__ __launch_bounds__(64) void k_adjoint_self(AdjArgs aa)
 {
     constexpr int ND = nd_of(D);
-    constexpr int NG = 6 * ND;
+    constexpr int R = (ND + 15) / 16;
+    constexpr int KP = 16 * R + 1;       // LDS doubles per node row of K (odd pitch)
+    constexpr int FP = 19;               // LDS doubles per node row of the weighted terms
+    __shared__ double s_pan[6][kPanW];
+    // chart and density coefficients, read at every node (kept out of registers)
+    __shared__ double s_cs[5 * ND];
+    __shared__ double s_k[64 * KP];
+    __shared__ double s_f[64 * FP];
     const QuadArgs &a = aa.qa;
     const int lane = threadIdx.x & 63;
+    const int a16 = lane & 15, grp = lane >> 4;
     const int nr = a.nr, na = a.na;
-    int singular = 0;
     for (int64_t idx = blockIdx.x; idx < a.count; idx += gridDim.x) {
         const int p = __builtin_amdgcn_readfirstlane(a.grp[a.seg + idx]);
         if (p < 0) continue;
@@ -616,19 +566,20 @@ __global__ __launch_bounds__(64) void k_adjoint_self(AdjArgs aa)
         const int64_t nb = a.pb.node_ptr[j];
         const int64_t node = a.pb.node_of_target[t];
         const int l = (int)(node - nb);
-        const double *cf = a.coef + 3 * nb;
-        const double *sc = aa.scoef + 2 * nb;
+        for (int k = lane; k < 3 * ND; k += 64) s_cs[k] = a.coef[3 * nb + k];
+        for (int k = lane; k < 2 * ND; k += 64) s_cs[3 * ND + k] = aa.scoef[2 * nb + k];
+        __syncthreads();
         const double lr = aa.lam[2 * t], li = -aa.lam[2 * t + 1];
         const double tu = a.tab.uv[D][2 * l], tv = a.tab.uv[D][2 * l + 1];
         double x[3], G00, G01, G11;
         {
             double K[ND], Xu[3], Xv[3];
-            chart_eval<D>(cf, tu, tv, K, x, Xu, Xv);
+            chart_eval<D>(s_cs, tu, tv, K, x, Xu, Xv);
             G00 = Xu[0] * Xu[0] + Xu[1] * Xu[1] + Xu[2] * Xu[2];
             G01 = Xu[0] * Xv[0] + Xu[1] * Xv[1] + Xu[2] * Xv[2];
             G11 = Xv[0] * Xv[0] + Xv[1] * Xv[1] + Xv[2] * Xv[2];
         }
-        double pA[6][2], pE[6][2], pmu[6], phl[6], pdet[6], pxa[6], pxb[6];
+        // panels exactly as in the forward self kernel
         int npan = 0;
         const double Pv[3][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}};
 #pragma unroll
@@ -647,62 +598,152 @@ __global__ __launch_bounds__(64) void k_adjoint_self(AdjArgs aa)
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
                 if (half == 1 && !split) break;
-                pA[npan][0] = Ax; pA[npan][1] = Ay; pE[npan][0] = Ex; pE[npan][1] = Ey;
-                pmu[npan] = mu; phl[npan] = h / L; pdet[npan] = det;
-                pxa[npan] = split ? (half == 0 ? x0 : 0.0) : x0;
-                pxb[npan] = split ? (half == 0 ? 0.0 : x1) : x1;
+                if (lane == 0) {
+                    double *pp = s_pan[npan];
+                    pp[0] = Ax; pp[1] = Ay; pp[2] = Ex; pp[3] = Ey;
+                    pp[4] = mu; pp[5] = h / L; pp[6] = det;
+                    pp[7] = split ? (half == 0 ? x0 : 0.0) : x0;
+                    pp[8] = split ? (half == 0 ? 0.0 : x1) : x1;
+                }
                 ++npan;
             }
         }
-        double GC[NG], T12[12];
+        __syncthreads();
+        // acc[r][18]: moments of the eighteen terms for basis a16 + 16 r over
+        // this lane's node class
+        double acc[R][18];
 #pragma unroll
-        for (int v = 0; v < NG; ++v) GC[v] = 0.0;
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int v = 0; v < 18; ++v) acc[r][v] = 0.0;
+        double T12[12];
 #pragma unroll
         for (int v = 0; v < 12; ++v) T12[v] = 0.0;
         const int per_panel = na * nr;
         const int total = npan * per_panel;
-        for (int q = lane; q < total; q += 64) {
-            const int pi = q / per_panel;
-            const int rem = q - pi * per_panel;
-            const int ia = rem / nr, ir = rem - ia * nr;
-            double Ax = 0, Ay = 0, Ex = 0, Ey = 0, mu = 0, hl = 0, det = 0, xa = 0, xb = 0;
+        const float inv_pp = 1.0f / (float)per_panel, inv_nr = 1.0f / (float)nr;
+        for (int base = 0; base < total; base += 64) {
+            const int q = base + lane;
+            double *kr = s_k + lane * KP;
+            double *fr = s_f + lane * FP;
+            if (q < total) {
+                const int pi = (int)(((float)q + 0.5f) * inv_pp);
+                const int rem = q - pi * per_panel;
+                const int ia = (int)(((float)rem + 0.5f) * inv_nr), ir = rem - ia * nr;
+                const double *pp = s_pan[pi];
+                const double Ax = pp[0], Ay = pp[1], Ex = pp[2], Ey = pp[3], mu = pp[4];
+                const double hl = pp[5], det = pp[6], xa = pp[7], xb = pp[8];
+                const double xi = xa + (xb - xa) * a.gla[2 * ia];
+                // sinh and cosh from one exponential (lam needs absolute accuracy)
+                const double ex = exp(xi), exi = 1.0 / ex;
+                const double lam = mu + hl * (0.5 * (ex - exi));
+                const double dlam = hl * (0.5 * (ex + exi)) * (xb - xa) * a.gla[2 * ia + 1];
+                const double s = a.glr[2 * ir], ws = a.glr[2 * ir + 1];
+                const double dx = Ax + lam * Ex - tu, dy = Ay + lam * Ey - tv;
+                const double u = tu + s * dx, v = tv + s * dy;
+                // chart, density and basis rows in one recurrence pass
+                double X[3] = {0.0, 0.0, 0.0}, Xu[3] = {0.0, 0.0, 0.0}, Xv[3] = {0.0, 0.0, 0.0};
+                double sgr = 0.0, sgi = 0.0;
+                const double *cs = s_cs;
+                asm volatile("" : "+v"(cs));
+                koorn_visit<D>(u, v, [&](int m, double k, double ku, double kv) {
+                    kr[m] = k;
 #pragma unroll
-            for (int k = 0; k < 6; ++k)
-                if (k == pi) {
-                    Ax = pA[k][0]; Ay = pA[k][1]; Ex = pE[k][0]; Ey = pE[k][1]; mu = pmu[k];
-                    hl = phl[k]; det = pdet[k]; xa = pxa[k]; xb = pxb[k];
+                    for (int c = 0; c < 3; ++c) {
+                        const double cf = cs[c * ND + m];
+                        X[c] = __builtin_fma(cf, k, X[c]);
+                        Xu[c] = __builtin_fma(cf, ku, Xu[c]);
+                        Xv[c] = __builtin_fma(cf, kv, Xv[c]);
+                    }
+                    sgr = __builtin_fma(cs[3 * ND + 2 * m], k, sgr);
+                    sgi = __builtin_fma(cs[3 * ND + 2 * m + 1], k, sgi);
+                });
+                const double n[3] = {Xu[1] * Xv[2] - Xu[2] * Xv[1], Xu[2] * Xv[0] - Xu[0] * Xv[2],
+                                     Xu[0] * Xv[1] - Xu[1] * Xv[0]};
+                double rhr, rhi;
+                cmul(lr, li, sgr, sgi, rhr, rhi);
+                NodeGrad g;
+                node_grad(a.kern, x, X, n, s * det * ws * dlam, rhr, rhi, g);
+                // weighted terms: gX, b = Xv x gn, d = gn x Xu; (c, re/im) order
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+                    fr[2 * c] = g.gXr[c];
+                    fr[2 * c + 1] = g.gXi[c];
+                    fr[6 + 2 * c] = Xv[c1] * g.gnr[c2] - Xv[c2] * g.gnr[c1];
+                    fr[6 + 2 * c + 1] = Xv[c1] * g.gni[c2] - Xv[c2] * g.gni[c1];
+                    fr[12 + 2 * c] = g.gnr[c1] * Xu[c2] - g.gnr[c2] * Xu[c1];
+                    fr[12 + 2 * c + 1] = g.gni[c1] * Xu[c2] - g.gni[c2] * Xu[c1];
+                    T12[2 * c] -= g.gXr[c];
+                    T12[2 * c + 1] -= g.gXi[c];
                 }
-            const double xi = xa + (xb - xa) * a.gla[2 * ia];
-            // sinh and cosh from one exponential (lam needs absolute accuracy)
-            const double ex = exp(xi), exi = 1.0 / ex;
-            const double lam = mu + hl * (0.5 * (ex - exi));
-            const double dlam = hl * (0.5 * (ex + exi)) * (xb - xa) * a.gla[2 * ia + 1];
-            const double s = a.glr[2 * ir], ws = a.glr[2 * ir + 1];
-            const double dx = Ax + lam * Ex - tu, dy = Ay + lam * Ey - tv;
-            double K[ND], Ku[ND], Kv[ND], X[3], Xu[3], Xv[3];
-            chart_eval_d<D>(cf, tu + s * dx, tv + s * dy, K, Ku, Kv, X, Xu, Xv);
-            const double n[3] = {Xu[1] * Xv[2] - Xu[2] * Xv[1], Xu[2] * Xv[0] - Xu[0] * Xv[2],
-                                 Xu[0] * Xv[1] - Xu[1] * Xv[0]};
-            double sgr, sgi, rhr, rhi;
-            sigma_at<ND>(sc, K, sgr, sgi);
-            cmul(lr, li, sgr, sgi, rhr, rhi);
-            NodeGrad gg;
-            node_grad(a.kern, x, X, n, s * det * ws * dlam, rhr, rhi, gg);
-            accumulate_node<ND>(gg, K, Ku, Kv, Xu, Xv, GC, T12);
-        }
-        double *dst = aa.gc_self + node * aa.self_pitch;
+                T12[6] += g.gkr;
+                T12[7] += g.gki;
+                T12[8] += g.sr;
+                T12[9] += g.si;
+                T12[10] += g.dr;
+                T12[11] += g.di;
+            } else {
 #pragma unroll
-        for (int v = 0; v < NG; ++v) {
-            const double tv2 = wave_sum(GC[v]);
-            if (lane == 0) dst[v] = tv2;
+                for (int v = 0; v < 18; ++v) fr[v] = 0.0;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            // transposed accumulation over the nodes of this lane's class
+            const int nq = total - base < 64 ? total - base : 64;
+            for (int i = grp; i < nq; i += 4) {
+                const double *f = s_f + i * FP;
+                const double *kb = s_k + i * KP;
+                double fv[18];
+#pragma unroll
+                for (int v = 0; v < 18; ++v) fv[v] = f[v];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double k = kb[a16 + 16 * r];
+#pragma unroll
+                    for (int v = 0; v < 18; ++v) acc[r][v] = __builtin_fma(fv[v], k, acc[r][v]);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+        // sum the four node classes; lanes of class 0 leave M[v][m] in LDS
+        double *sm = s_k;   // [18][ND], free after the last chunk
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int v = 0; v < 18; ++v) {
+                double w = acc[r][v] + __shfl_xor(acc[r][v], 16, 64);
+                w += __shfl_xor(w, 32, 64);
+                const int m = a16 + 16 * r;
+                if (grp == 0 && m < ND) sm[v * ND + m] = w;
+            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        // GC[(c * ND + a) * 2 + re/im] = M[gX] + Du M[b] + Dv M[d]; v = 2 c + re/im
+        {
+            double *dst = aa.gc_self + node * aa.self_pitch;
+            const double *Du = a.tab.D[D], *Dv = a.tab.D[D] + ND * ND;
+            for (int o = lane; o < 6 * ND; o += 64) {
+                const int v = o / ND, m0 = o - v * ND;
+                double w = sm[v * ND + m0];
+                const double *mb = sm + (6 + v) * ND, *md = sm + (12 + v) * ND;
+                for (int m = 0; m < ND; ++m)
+                    w = __builtin_fma(Du[m0 * ND + m], mb[m], __builtin_fma(Dv[m0 * ND + m], md[m], w));
+                dst[2 * ((v >> 1) * ND + m0) + (v & 1)] = w;
+            }
         }
 #pragma unroll
         for (int v = 0; v < 12; ++v) {
             const double tv2 = wave_sum(T12[v]);
             if (lane == 0) aa.t_pair[(int64_t)p * 12 + v] = tv2;
         }
+        // the next pair overwrites s_pan and s_cs
+        __syncthreads();
     }
-    (void)singular;
 }
 
 // sigma coefficients per patch: s = V sigma_j (complex).
