@@ -604,12 +604,15 @@ __device__ __forceinline__ void reduce_scatter_rows(double *acc, int lane)
 }
 
 // Self quadrature.  One wavefront per target; the target-split rule's nodes
-// are taken 64 at a time (one per lane): each lane evaluates chart, kernel and
-// basis at its node and stages K and the weighted kernel value in LDS; then
-// lane v accumulates component v of the moments over the 64 staged nodes.
-// No per-lane moment vector is kept in registers.
+// are taken 64 at a time (one per lane), and each lane evaluates chart,
+// kernel and basis at its node.  Small degrees (moment vector <= 32 doubles)
+// accumulate per lane in registers and reduce-scatter over the wavefront
+// once per target, at two wavefronts per SIMD; larger degrees stage K and the
+// weighted kernel value in LDS, and lane v accumulates component v of the
+// moments over the 64 staged nodes.
 template <int D, bool CPLX>
-__global__ __launch_bounds__((64 * SelfShape<D, CPLX>::WPB)) void k_self(QuadArgs a)
+__global__ __launch_bounds__((64 * SelfShape<D, CPLX>::WPB))
+__attribute__((amdgpu_waves_per_eu(D <= 4 ? 2 : 1))) void k_self(QuadArgs a)
 {
     using S = SelfShape<D, CPLX>;
     constexpr int ND = S::ND, NV = S::NV, RP = S::RP, WPB = S::WPB;
