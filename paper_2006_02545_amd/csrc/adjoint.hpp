@@ -566,7 +566,8 @@ __global__ __launch_bounds__(64) void k_adjoint_self(AdjArgs aa)
         const int64_t nb = a.pb.node_ptr[j];
         const int64_t node = a.pb.node_of_target[t];
         const int l = (int)(node - nb);
-        for (int k = lane; k < 3 * ND; k += 64) s_cs[k] = a.coef[3 * nb + k];
+        // chart relative to its constant term, as in the forward self kernel
+        for (int k = lane; k < 3 * ND; k += 64) s_cs[k] = a.coef_rel[3 * nb + k];
         for (int k = lane; k < 2 * ND; k += 64) s_cs[3 * ND + k] = aa.scoef[2 * nb + k];
         __syncthreads();
         const double lr = aa.lam[2 * t], li = -aa.lam[2 * t + 1];

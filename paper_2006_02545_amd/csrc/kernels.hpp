@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_group(int64_t np, const int32_t *pair_p
 
 template <int D>
 __device__ void prep_patch(const Problem &pb, const DegTab &tab, int64_t j, double tol_scale,
-                           double *coef, double *tau, double *rho, int *flags)
+                           double *coef, double *coef_rel, double *tau, double *rho, int *flags)
 {
     constexpr int ND = nd_of(D);
     const double *V = tab.V[D];
@@ -262,6 +262,10 @@ __device__ void prep_patch(const Problem &pb, const DegTab &tab, int64_t j, doub
         cf[0 * ND + a] = s0;
         cf[1 * ND + a] = s1;
         cf[2 * ND + a] = s2;
+        double *cr = coef_rel + 3 * pb.node_ptr[j];
+        cr[0 * ND + a] = a == 0 ? 0.0 : s0;
+        cr[1 * ND + a] = a == 0 ? 0.0 : s1;
+        cr[2 * ND + a] = a == 0 ? 0.0 : s2;
     }
     // d_j = min_l sqrt(J(u_l, v_l) |w_l|)  (Section 4.2)
     double dj = 1e300;
@@ -286,20 +290,20 @@ __device__ void prep_patch(const Problem &pb, const DegTab &tab, int64_t j, doub
     rho[j] = rh;
 }
 
-__global__ void k_prep(Problem pb, DegTab tab, double tol_scale, double *coef, double *tau,
-                       double *rho, int *flags)
+__global__ void k_prep(Problem pb, DegTab tab, double tol_scale, double *coef, double *coef_rel,
+                       double *tau, double *rho, int *flags)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= pb.P) return;
     switch (pb.degree[j]) {
-    case 1: prep_patch<1>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
-    case 2: prep_patch<2>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
-    case 3: prep_patch<3>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
-    case 4: prep_patch<4>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
-    case 5: prep_patch<5>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
-    case 6: prep_patch<6>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
-    case 7: prep_patch<7>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
-    case 8: prep_patch<8>(pb, tab, j, tol_scale, coef, tau, rho, flags); break;
+    case 1: prep_patch<1>(pb, tab, j, tol_scale, coef, coef_rel, tau, rho, flags); break;
+    case 2: prep_patch<2>(pb, tab, j, tol_scale, coef, coef_rel, tau, rho, flags); break;
+    case 3: prep_patch<3>(pb, tab, j, tol_scale, coef, coef_rel, tau, rho, flags); break;
+    case 4: prep_patch<4>(pb, tab, j, tol_scale, coef, coef_rel, tau, rho, flags); break;
+    case 5: prep_patch<5>(pb, tab, j, tol_scale, coef, coef_rel, tau, rho, flags); break;
+    case 6: prep_patch<6>(pb, tab, j, tol_scale, coef, coef_rel, tau, rho, flags); break;
+    case 7: prep_patch<7>(pb, tab, j, tol_scale, coef, coef_rel, tau, rho, flags); break;
+    case 8: prep_patch<8>(pb, tab, j, tol_scale, coef, coef_rel, tau, rho, flags); break;
     default: flags[kFlagNotRegistered] = 1; break;
     }
 }
@@ -322,6 +326,10 @@ struct QuadArgs {
     const int32_t *pair_tgt, *pair_patch;
     const int64_t *pair_off;
     const double *coef;
+    // the same coefficients without the constant term (basis 0): positions
+    // relative to it, of the patch's size rather than the surface's, so that
+    // x - y near a self target keeps its digits
+    const double *coef_rel;
     const double *tau;
     const double *rho;    // max_l |x_l| per patch (coordinate scale)
     double *val;
@@ -635,8 +643,9 @@ __attribute__((amdgpu_waves_per_eu(D <= 4 ? 2 : 1))) void k_self(QuadArgs a)
         const int j = __builtin_amdgcn_readfirstlane(a.pair_patch[p]);
         const int64_t nb = a.pb.node_ptr[j];
         const int l = (int)(a.pb.node_of_target[t] - nb);
-        // chart coefficients in LDS, read at every node (kept out of registers)
-        for (int k = lane; k < 3 * ND; k += 64) s_cfw[wv][k] = a.coef[3 * nb + k];
+        // chart coefficients (relative to the constant term) in LDS, read at
+        // every node (kept out of registers)
+        for (int k = lane; k < 3 * ND; k += 64) s_cfw[wv][k] = a.coef_rel[3 * nb + k];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

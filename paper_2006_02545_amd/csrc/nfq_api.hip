@@ -43,7 +43,7 @@ struct nfq_plan {
     int64_t seg_start_h[18] = {}, seg_len_h[18] = {}, count_h[18] = {};
     int64_t *seg_start = nullptr;
     unsigned long long *cursor = nullptr;
-    double *coef = nullptr, *tau = nullptr, *rho = nullptr;
+    double *coef = nullptr, *coef_rel = nullptr, *tau = nullptr, *rho = nullptr;
     double *stack = nullptr;
     int64_t stack_waves = 0;
     int *flags = nullptr;
@@ -381,7 +381,7 @@ static nfq_status prepare(nfq_plan *pl, const nfq_kernel *kern, const nfq_params
     DegTab tab = make_tab(ctx);
     tm.begin(kPhPrep, 0, st);
     hipLaunchKernelGGL(k_prep, dim3(nblk(pb.P, 64)), dim3(64), 0, st, pb, tab,
-                       prm->loosen * prm->tol, pl->coef, pl->tau, pl->rho, pl->flags);
+                       prm->loosen * prm->tol, pl->coef, pl->coef_rel, pl->tau, pl->rho, pl->flags);
     tm.end(kPhPrep, 0, st);
     // quadratures and weights, per degree
     qa.pb = pb;
@@ -397,6 +397,7 @@ static nfq_status prepare(nfq_plan *pl, const nfq_kernel *kern, const nfq_params
     qa.pair_patch = pl->pair_patch;
     qa.pair_off = pl->pair_off;
     qa.coef = pl->coef;
+    qa.coef_rel = pl->coef_rel;
     qa.tau = pl->tau;
     qa.rho = pl->rho;
     qa.val = (double *)val;
@@ -528,7 +529,7 @@ void nfq_plan_destroy(nfq_plan *pl)
     if (!pl) return;
     (void)hipSetDevice(pl->ctx->device);
     void *ptrs[] = {pl->rowlen, pl->npair, pl->pair_ptr, pl->pair_tgt, pl->pair_patch, pl->pair_self,
-                    pl->pair_off, pl->grp, pl->seg_start, pl->cursor, pl->coef, pl->tau, pl->rho, pl->stack,
+                    pl->pair_off, pl->grp, pl->seg_start, pl->cursor, pl->coef, pl->coef_rel, pl->tau, pl->rho, pl->stack,
                     pl->flags, pl->stats, pl->counts};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -651,6 +652,7 @@ nfq_status nfq_plan_create(nfq_ctx *ctx, const nfq_surface *surf, const nfq_targ
     PL_TRY(dalloc(&pl->grp, pl->grp_len));
     PL_TRY(hipMemcpy(pl->seg_start, pl->seg_start_h, sizeof(pl->seg_start_h), hipMemcpyHostToDevice));
     PL_TRY(dalloc(&pl->coef, 3 * pb.N));
+    PL_TRY(dalloc(&pl->coef_rel, 3 * pb.N));
     PL_TRY(dalloc(&pl->tau, pb.P));
     PL_TRY(dalloc(&pl->rho, pb.P));
     // patch-major work items of the near kernel: sized here, built in generate

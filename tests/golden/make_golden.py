@@ -38,6 +38,9 @@ WORKLOADS = {
     "cfie_sphere1280_d4": (lambda: S.config(1), 160),
     "cfie_sphere320_d4_k5": (lambda: S.config(3), 120),
     "mixed_small_d1to8": (small_mixed, 160),
+    # full-size workloads, sampled rows
+    "mixed_ellipsoid_torus": (lambda: S.config(2), 48),
+    "star200k_d6": (lambda: S.config(4), 24),
 }
 
 
@@ -72,7 +75,9 @@ def make(name, workers=8):
         targets = np.arange(prob.NT)
     else:
         targets = np.sort(np.random.default_rng(12345).choice(prob.NT, nsamp, replace=False))
-    chunks = [(name, c) for c in np.array_split(targets, workers * 4) if len(c)]
+    # large surfaces take a while to build: one chunk per worker there
+    nchunk = workers if prob.P > 50000 else workers * 4
+    chunks = [(name, c) for c in np.array_split(targets, nchunk) if len(c)]
     with ProcessPoolExecutor(workers) as ex:
         res = [r for part in ex.map(_rows, chunks) for r in part]
     res.sort(key=lambda r: r[0])
