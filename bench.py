@@ -84,8 +84,8 @@ def cpu_baseline(seconds, workers):
 # --copy-calibration 1024: FETCH_SIZE reads 0.5 GiB, WRITE_SIZE 1 GiB), valid
 # for the kernel sources with this digest.
 TRAFFIC_RECORD = {
-    "sources_sha256": "93711910743a31e07b810c7766dd89b20ebecb020297407796ee4c407de8e3b6",
-    "fetch_kib": 178196.3, "write_kib": 374789.5,
+    "sources_sha256": "6f097a80142ecf755a73b250ec30577099eb14ec78991dc00ede8ead9164a540",
+    "fetch_kib": 178838.2, "write_kib": 374700.3,
     "fetch_scale": 2.0, "write_scale": 1.0,
 }
 NEAR_SOURCES = ["near_patch.hpp", "kernels.hpp", "device.hpp", "fastmath.hpp", "koorn.hpp"]
