@@ -163,6 +163,42 @@ def main():
     ms = (t1 - t0) / args.steps * 1e3
     value = prob.NT / (ms * 1e-3)
 
+    # the same generate captured once in a HIP graph and replayed (a plan of
+    # its own, on the capture stream); per-replay durations from events
+    graph = None
+    try:
+        gs = torch.cuda.Stream()
+        ctx_g = nfq.Context(0, stream=gs)
+        plan_g = nfq.plan_for(ctx_g, prob)
+        col_g = torch.empty_like(col)
+        val_g = torch.empty_like(val)
+        gen_g = dict(gen, col=col_g, val=val_g, stats=False)
+        with torch.cuda.stream(gs):
+            plan_g.generate(**gen_g)
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr, stream=gs):
+            plan_g.generate(**gen_g)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(max(10, args.steps)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(gs):
+                e0.record(gs)
+                gr.replay()
+                e1.record(gs)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        times.sort()
+        med = times[len(times) // 2]
+        same = bool(torch.equal(val_g.view(torch.float64), val.view(torch.float64)))
+        graph = {"value": prob.NT / (med * 1e-3), "unit": "target-points/s", "ms_median": med,
+                 "replays": len(times), "matches_eager": same}
+        del gr
+    except RuntimeError as exc:  # capture refused: report, keep the eager figures
+        graph = {"error": str(exc)[:200]}
+
     # forward + adjoint: generate, apply and the adjoint (gradient of
     # conj(lambda)^T A sigma wrt node coordinates, k, alpha, beta)
     sig_t = torch.as_tensor(prob.sigma, dtype=torch.complex128, device="cuda")
@@ -238,6 +274,7 @@ def main():
                         "step": "generate + apply + adjoint (gradient wrt nodes, k, alpha, beta)"},
         "per_pair_path": {"value": prob.NT / (ms_pp * 1e-3), "unit": "target-points/s",
                           "ms_per_step": ms_pp, "steps": npp},
+        "graph_replay": graph,
         "phase_ms": phases,
         "gen_stats": {k: st[k] for k in ("near_pairs", "self_pairs", "visits", "checks",
                                          "nonconverged", "max_level")},

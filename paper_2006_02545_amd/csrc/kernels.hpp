@@ -70,6 +70,16 @@ __device__ __forceinline__ int64_t patch_of_node(const int64_t *node_ptr, int64_
     return lo;
 }
 
+// Fills n 32-bit words with v.  The generate sequence clears its counters and
+// flags with this kernel rather than with memset nodes, so that it can be
+// captured in a graph and replayed.
+__global__ __launch_bounds__(256) void k_fill32(int64_t n, uint32_t v, uint32_t *p)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 // ---------------------------------------------------------------- builder
 
 // Row lengths of the output CSR and number of (target, patch) blocks per

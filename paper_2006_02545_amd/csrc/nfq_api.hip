@@ -127,6 +127,15 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (
 
 int64_t pad16(int64_t n) { return (n + 15) / 16 * 16; }
 
+// Fill `bytes` (a multiple of 4) at p with the 32-bit word v, as a kernel.
+void fill32(void *p, int64_t bytes, uint32_t v, hipStream_t st)
+{
+    const int64_t n = bytes / 4;
+    if (n <= 0) return;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill32, dim3(blocks), dim3(256), 0, st, n, v, (uint32_t *)p);
+}
+
 // Exclusive scan of a_in, b_in (length n) into a_out, b_out (length n + 1).
 nfq_status run_scan(nfq_plan *pl, int64_t n, const int64_t *a_in, const int64_t *b_in,
                     int64_t *a_out, int64_t *b_out, std::vector<int64_t *> &tmp)
@@ -202,9 +211,9 @@ nfq_status build_items(nfq_plan *pl, hipStream_t st)
 {
     nfq_ctx *ctx = pl->ctx;
     const int64_t P = pl->pb.P, np = pl->npairs;
-    HIP_TRY(ctx, hipMemsetAsync(pl->pcount, 0, P * 8, st));
-    HIP_TRY(ctx, hipMemsetAsync(pl->pcursor, 0, P * 8, st));
-    HIP_TRY(ctx, hipMemsetAsync(pl->item_cursor, 0, 9 * 8, st));
+    fill32(pl->pcount, P * 8, 0u, st);
+    fill32(pl->pcursor, P * 8, 0u, st);
+    fill32(pl->item_cursor, 9 * 8, 0u, st);
     if (np > 0)
         hipLaunchKernelGGL(k_patch_count, dim3(nblk(np, 256)), dim3(256), 0, st, np, pl->pair_patch,
                            pl->pair_self, pl->pcount);
@@ -353,10 +362,10 @@ static nfq_status prepare(nfq_plan *pl, const nfq_kernel *kern, const nfq_params
     hipStream_t st = ctx->stream;
     const Problem &pb = pl->pb;
     const int64_t NT = pb.NT;
-    HIP_TRY(ctx, hipMemsetAsync(pl->flags, 0, kNumFlags * sizeof(int), st));
-    HIP_TRY(ctx, hipMemsetAsync(pl->stats, 0, kNumStats * 8, st));
-    HIP_TRY(ctx, hipMemsetAsync(pl->cursor, 0, 18 * 8, st));
-    HIP_TRY(ctx, hipMemsetAsync(pl->grp, 0xff, pl->grp_len * sizeof(int32_t), st));
+    fill32(pl->flags, kNumFlags * sizeof(int), 0u, st);
+    fill32(pl->stats, kNumStats * 8, 0u, st);
+    fill32(pl->cursor, 18 * 8, 0u, st);
+    fill32(pl->grp, pl->grp_len * sizeof(int32_t), 0xffffffffu, st);
     // pair / work-queue builder
     tm.begin(kPhBuilder, 0, st);
     if (NT > 0)
