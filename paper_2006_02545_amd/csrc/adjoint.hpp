@@ -162,7 +162,7 @@ __device__ __forceinline__ void sigma_at(const double *sc, const double *K, doub
 // The chart-coefficient gradient follows at the end from the differentiation
 // matrices of the basis:  dPhi/dchi_c = M[gX_c] + Du M[b_c] + Dv M[d_c].
 template <int D>
-__global__ __launch_bounds__(256) void k_adjoint_patch(AdjArgs aa)
+__global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_adjoint_patch(AdjArgs aa)
 {
     using S = PatchShape<D, true>;
     constexpr int ND = S::ND, W = S::W, PL = S::PL, G0 = S::G0, KS = S::KS, R = S::R;
