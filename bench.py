@@ -8,7 +8,9 @@ lists) are resident in device memory before timing starts.
 
 Workload: Helmholtz combined field D - ik S, k = 2 pi, unit sphere with 1280
 quadratic patches at degree 4 (15 nodes, 19,200 on-surface targets), near
-radius 1.25 R_j, tol 1e-8, complex128.
+radius 1.25 R_j, tol 1e-8, complex128.  --workload times the generate step of
+the full-size mixed-degree ellipsoid + torus (6000 patches, degrees 2..8) or
+the 200,000-patch star surface (degree 6, tol 1e-9) instead.
 
 Prints one JSON line (see the field list at the end of main()).
 """
@@ -37,15 +39,20 @@ def kernel_flops(prob):
     return C_KERNEL["laplace"] if prob.real_kernel else C_KERNEL["laplace_cplx"]
 
 
+# workloads that bench.py can time; the first is the default bench line, the
+# others are the full-size mixed-degree and 200,000-patch runs
+WORKLOADS = {"cfie_sphere1280_d4": 1, "mixed_ellipsoid_torus": 2, "star200k_d6": 4}
+
+
 def _oracle_rows(args):
     """Worker: whole rows (near + self blocks) of randomly chosen targets of the
     workload, oracle method mode, until `seconds` are spent.  Returns the
     number of rows done and the seconds taken."""
-    seed, seconds = args
+    seed, seconds, cfg = args
     import numpy as np
     import oracle
     from paper_2006_02545_amd import surfaces
-    prob = surfaces.config(1)
+    prob = surfaces.config(cfg)
     run = oracle.OracleRun(prob, mode=oracle.METHOD)
     order = np.random.default_rng(seed).permutation(prob.NT)
     done = 0
@@ -60,16 +67,16 @@ def _oracle_rows(args):
     return done, time.perf_counter() - t0
 
 
-def cpu_baseline(seconds, workers):
+def cpu_baseline(seconds, workers, cfg=1):
     """The oracle on the host: `workers` processes (one thread each), each on
     its own random sample of target rows for about `seconds`."""
     import multiprocessing as mp
     if workers <= 1:
-        done, el = _oracle_rows((2024, seconds))
+        done, el = _oracle_rows((2024, seconds, cfg))
         rate = done / el
     else:
         with mp.get_context("spawn").Pool(workers) as pool:
-            res = pool.map(_oracle_rows, [(2024 + i, seconds) for i in range(workers)])
+            res = pool.map(_oracle_rows, [(2024 + i, seconds, cfg) for i in range(workers)])
         done = sum(r[0] for r in res)
         rate = sum(r[0] / r[1] for r in res)
         el = max(r[1] for r in res)
@@ -84,8 +91,8 @@ def cpu_baseline(seconds, workers):
 # --copy-calibration 1024: FETCH_SIZE reads 0.5 GiB, WRITE_SIZE 1 GiB), valid
 # for the kernel sources with this digest.
 TRAFFIC_RECORD = {
-    "sources_sha256": "6f097a80142ecf755a73b250ec30577099eb14ec78991dc00ede8ead9164a540",
-    "fetch_kib": 178838.2, "write_kib": 374700.3,
+    "sources_sha256": "cfbfe41a871622c4ffcace426572b48f7d35a2370a2c3e9f3c9d8b7d77460d01",
+    "fetch_kib": 178853.3, "write_kib": 374629.3,
     "fetch_scale": 2.0, "write_scale": 1.0,
 }
 NEAR_SOURCES = ["near_patch.hpp", "kernels.hpp", "device.hpp", "fastmath.hpp", "koorn.hpp"]
@@ -118,6 +125,9 @@ def main():
     ap.add_argument("--print-digest", action="store_true",
                     help="print the digest of the near-kernel sources and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="cfie_sphere1280_d4", choices=list(WORKLOADS),
+                    help="workload to time (default: the bench line's); the others time the "
+                         "generate step only")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -144,7 +154,8 @@ def main():
     import torch
     from paper_2006_02545_amd import nfq, surfaces
 
-    prob = surfaces.config(1)
+    main_line = args.workload == "cfie_sphere1280_d4"
+    prob = surfaces.config(WORKLOADS[args.workload])
     torch.cuda.set_device(0)
     ctx = nfq.Context(0)
     plan = nfq.plan_for(ctx, prob)
@@ -167,6 +178,8 @@ def main():
     # its own, on the capture stream); per-replay durations from events
     graph = None
     try:
+        if not main_line:
+            raise StopIteration
         gs = torch.cuda.Stream()
         ctx_g = nfq.Context(0, stream=gs)
         plan_g = nfq.plan_for(ctx_g, prob)
@@ -196,6 +209,8 @@ def main():
         graph = {"value": prob.NT / (med * 1e-3), "unit": "target-points/s", "ms_median": med,
                  "replays": len(times), "matches_eager": same}
         del gr
+    except StopIteration:        # timed on the default workload only
+        graph = None
     except RuntimeError as exc:  # capture refused: report, keep the eager figures
         graph = {"error": str(exc)[:200]}
 
@@ -212,26 +227,30 @@ def main():
         plan.apply(col, val, sig_t)
         plan.adjoint_into(prob.alpha, prob.beta, prob.k, prob.tol, sig_t, lam_t, grad, gk, dab)
 
-    fwd_adj()
-    torch.cuda.synchronize()
-    nfa = max(1, args.steps // 2)
-    t0 = time.perf_counter()
-    for _ in range(nfa):
+    nfa = max(1, args.steps // 2) if main_line else 0
+    ms_fa = None
+    if nfa:
         fwd_adj()
-    torch.cuda.synchronize()
-    ms_fa = (time.perf_counter() - t0) / nfa * 1e3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nfa):
+            fwd_adj()
+        torch.cuda.synchronize()
+        ms_fa = (time.perf_counter() - t0) / nfa * 1e3
 
     # the plain per-pair GPU path (one wavefront per pair, no reuse of
     # subtriangle geometry across targets) on the same workload
-    for _ in range(2):
-        plan.generate(stats=False, per_pair=True, **gen)
-    torch.cuda.synchronize()
-    npp = max(1, args.steps // 2)
-    t0 = time.perf_counter()
-    for _ in range(npp):
-        plan.generate(stats=False, per_pair=True, **gen)
-    torch.cuda.synchronize()
-    ms_pp = (time.perf_counter() - t0) / npp * 1e3
+    npp = max(1, args.steps // 2) if main_line else 0
+    ms_pp = None
+    if npp:
+        for _ in range(2):
+            plan.generate(stats=False, per_pair=True, **gen)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(npp):
+            plan.generate(stats=False, per_pair=True, **gen)
+        torch.cuda.synchronize()
+        ms_pp = (time.perf_counter() - t0) / npp * 1e3
 
     # per-phase durations from HIP events recorded on the library's stream
     phases = {k: 0.0 for k in ("ms_builder", "ms_prep", "ms_self", "ms_near", "ms_weights")}
@@ -241,17 +260,21 @@ def main():
         _, _, st = plan.generate(stats=True, timing=True, **gen)
         for k in phases:
             phases[k] += st[k] / nrep
-    nd = (int(prob.degree[0]) + 1) * (int(prob.degree[0]) + 2) // 2
-    nq = 64
-    # algorithmic flops of the adaptive near kernel (dominant): every
-    # subtriangle visit of every pair evaluates the kernel at nq nodes and
-    # accumulates nd complex moments
-    flops_near = st["visits"] * nq * (kernel_flops(prob) + 4 * nd)
-    achieved = flops_near / (phases["ms_near"] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "k_near (adaptive near quadrature)",
-                "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": near_traffic(),
-                "flops_per_launch": flops_near, "ms_per_launch": phases["ms_near"]}
+    roofline = None
+    degs = sorted(set(int(d) for d in prob.degree))
+    if len(degs) == 1:
+        nd = (degs[0] + 1) * (degs[0] + 2) // 2
+        nq = 64
+        # algorithmic flops of the adaptive near kernel (dominant): every
+        # subtriangle visit of every pair evaluates the kernel at nq nodes and
+        # accumulates nd complex moments
+        flops_near = st["visits"] * nq * (kernel_flops(prob) + 4 * nd)
+        achieved = flops_near / (phases["ms_near"] * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": "k_near (adaptive near quadrature)",
+                    "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / PEAK_FP64_TFLOPS,
+                    "traffic": near_traffic() if main_line else None,
+                    "flops_per_launch": flops_near, "ms_per_launch": phases["ms_near"]}
     out = {
         "metric": METRIC,
         "value": value,
@@ -265,15 +288,17 @@ def main():
         "vs_baseline": None,
         "dtype": "complex128",
         "data": "synthetic",
-        "config": {"workload": "cfie_sphere1280_d4", "patches": prob.P, "degree": int(prob.degree[0]),
+        "config": {"workload": args.workload, "patches": prob.P,
+                   "degree": degs[0] if len(degs) == 1 else "%d..%d" % (degs[0], degs[-1]),
                    "targets": prob.NT, "near_pairs": int(prob.near_patch.size),
                    "kernel": "D - ik S", "k": prob.k.real, "tol": prob.tol, "eta": prob.eta,
                    "loosen": 1.0, "global_batch": prob.NT, "parallelism": "single-gpu"},
-        "fwd_adjoint": {"value": prob.NT / (ms_fa * 1e-3), "unit": "target-points/s",
-                        "ms_per_step": ms_fa, "steps": nfa,
-                        "step": "generate + apply + adjoint (gradient wrt nodes, k, alpha, beta)"},
-        "per_pair_path": {"value": prob.NT / (ms_pp * 1e-3), "unit": "target-points/s",
-                          "ms_per_step": ms_pp, "steps": npp},
+        "fwd_adjoint": None if ms_fa is None else {
+            "value": prob.NT / (ms_fa * 1e-3), "unit": "target-points/s", "ms_per_step": ms_fa,
+            "steps": nfa, "step": "generate + apply + adjoint (gradient wrt nodes, k, alpha, beta)"},
+        "per_pair_path": None if ms_pp is None else {
+            "value": prob.NT / (ms_pp * 1e-3), "unit": "target-points/s", "ms_per_step": ms_pp,
+            "steps": npp},
         "graph_replay": graph,
         "phase_ms": phases,
         "gen_stats": {k: st[k] for k in ("near_pairs", "self_pairs", "visits", "checks",
@@ -282,7 +307,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or max(1, min(16, os.cpu_count() or 1))
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, workers)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, workers, WORKLOADS[args.workload])
     print(json.dumps(out))
 
 
