@@ -371,7 +371,9 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                 node_geometry<D, CPLX>(cf, Ax, Ay, Bx, By, Cx, Cy, a.rule[3 * q], a.rule[3 * q + 1],
                                        a.rule[3 * q + 2] * area, s_geo + tid * GS, tid & 15);
             }
-            __syncthreads();
+            // a single-target group reads only each thread's own node row
+            // (wavefront c takes child c, lane q node q): no exchange needed
+            if (__builtin_popcountll(e.mask) != 1) __syncthreads();
             const double thr = tau * __builtin_ldexp(1.0, -2 * e.level);
             const int L = e.level;
             // the wavefront that takes the first target of this group (varies
