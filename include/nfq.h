@@ -201,6 +201,27 @@ nfq_status nfq_adjoint(nfq_plan *plan, const nfq_kernel *kern, const nfq_params 
  * errors of earlier calls. */
 nfq_status nfq_sync(nfq_ctx *ctx);
 
+/* Near lists T_eta(x_t) on the device (near-field definitions of Section 4;
+ * lists by target, Section 5.2), in the nfq_nearlist layout that
+ * nfq_plan_create takes.  Patch j's ball has centre c_j = parametric mean of
+ * the chart, (1/|T0|) int_T0 X^j du dv, and radius R_j = max |X^j(u,v) - c_j|
+ * over the lattice (i/64, k/64), i + k <= 64, of T0; target t is near patch
+ * j when |x_t - c_j| < eta R_j and j is not the target's own patch.
+ * Arguments: surf, targets as for nfq_plan_create (device arrays; the
+ * degrees must be registered); eta > 0; row_ptr: caller-allocated device
+ * int64 [NT+1], always written on success and on the capacity error;
+ * patch: caller-allocated device int32 [capacity] (may be NULL when capacity
+ * is 0), rows strictly ascending; *nnz_out (host): number of near pairs;
+ * centres [P][3], radii [P]: device outputs or NULL.  When nnz exceeds
+ * capacity nothing is written to patch and the call returns
+ * NFQ_ERR_INVALID_ARG with *nnz_out set: call again with capacity >= nnz.
+ * Allocates its scratch and frees it before returning; synchronises the
+ * stream.  Deterministic.  Errors: INVALID_ARG (sizes, eta, null arrays,
+ * non-finite targets, capacity), NOT_REGISTERED, OUT_OF_MEMORY, HIP_ERROR. */
+nfq_status nfq_near_lists(nfq_ctx *ctx, const nfq_surface *surf, const nfq_targets *targets,
+                          double eta, int64_t *row_ptr, int32_t *patch, int64_t capacity,
+                          int64_t *nnz_out, double *centres, double *radii);
+
 void nfq_plan_destroy(nfq_plan *plan);
 const char *nfq_status_str(nfq_status s);
 const char *nfq_last_error(nfq_ctx *ctx);

@@ -1032,6 +1032,41 @@ int orc_patch_info(const orc_problem *pb, int64_t j, double *dj, double *normV)
     return 0;
 }
 
+/* Bounding ball of patch j for the near-field definitions of Section 4.
+ * Centre: the parametric mean of the chart, (1/|T0|) int_T0 X du dv,
+ * integrated with the conical rule of 8 x 8 points (exact for polynomials of
+ * degree <= 15 >= d).  Radius: the largest |X(u,v) - c| over the lattice
+ * (i/lat, k/lat), i + k <= lat, of T0, corners and edges included. */
+int orc_patch_ball(const orc_problem *pb, int64_t j, int lat, double *c3, double *R)
+{
+    patch_t pt;
+    if (setup_patch(pb, j, &pt)) return -1;
+    double rule[64 * 3];
+    if (orc_conical_rule(8, rule)) return -2;
+    long double c[3] = {0, 0, 0}, area = 0;
+    for (int q = 0; q < 64; ++q) {
+        geo_t g;
+        chart(&pt, rule[3 * q], rule[3 * q + 1], &g, NULL);
+        for (int a = 0; a < 3; ++a) c[a] += rule[3 * q + 2] * g.X[a];
+        area += rule[3 * q + 2];
+    }
+    for (int a = 0; a < 3; ++a) c3[a] = (double)(c[a] / area);
+    double r2 = 0.0;
+    for (int i = 0; i <= lat; ++i)
+        for (int k = 0; i + k <= lat; ++k) {
+            geo_t g;
+            chart(&pt, (double)i / lat, (double)k / lat, &g, NULL);
+            double s = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double d = (double)g.X[a] - c3[a];
+                s += d * d;
+            }
+            if (s > r2) r2 = s;
+        }
+    *R = sqrt(r2);
+    return 0;
+}
+
 /* Chart evaluation for tests: X, X_u, X_v of patch j at (u,v). */
 int orc_chart(const orc_problem *pb, int64_t j, double u, double v, double *out9)
 {

@@ -12,7 +12,7 @@ import subprocess
 import numpy as np
 
 __all__ = ["build", "lib", "koornwinder", "gauss_jacobi", "conical_rule", "reference",
-           "OracleRun", "METHOD", "TRUTH", "apply"]
+           "OracleRun", "METHOD", "TRUTH", "apply", "near_lists"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nfq_oracle.c")
@@ -79,6 +79,7 @@ def _bind(L):
     L.orc_apply.argtypes = [i64, vp, vp, vp, vp, vp]
     L.orc_patch_info.argtypes = [vp, i64, vp, vp]
     L.orc_chart.argtypes = [vp, i64, dbl, dbl, vp]
+    L.orc_patch_ball.argtypes = [vp, i64, i32, vp, vp]
     L.orc_set_trace.argtypes = [vp, i64]
     L.orc_set_trace.restype = None
     L.orc_trace_count.argtypes = []
@@ -211,10 +212,45 @@ class OracleRun:
         lib().orc_patch_info(C.byref(self.s), int(j), _p(dj), _p(nv))
         return float(dj[0]), float(nv[0])
 
+    def ball(self, j, lattice=64):
+        """Centre (parametric mean of the chart) and radius (max over the
+        lattice of T0) of patch j's bounding ball."""
+        c, R = np.zeros(3), np.zeros(1)
+        if lib().orc_patch_ball(C.byref(self.s), int(j), int(lattice), _p(c), _p(R)):
+            raise RuntimeError("patch %d not set up" % j)
+        return c, float(R[0])
+
     def chart(self, j, u, v):
         out = np.zeros(9)
         lib().orc_chart(C.byref(self.s), int(j), float(u), float(v), _p(out))
         return out[:3], out[3:6], out[6:]
+
+
+def near_lists(prob, eta, centres, radii):
+    """T_eta(x_t) by brute force (near-field definitions of Section 4): for
+    every target, the patches j with |x_t - c_j| < eta R_j, own patch
+    excluded, ascending; the balls (c_j, R_j) come from OracleRun.ball.
+    Returns (row_ptr, patch, margin): margin[t] is the smallest
+    | |x_t - c_j| - eta R_j | / R_j over all patches j, since a target that
+    close to a ball's sphere can fall either way under rounding."""
+    x = np.asarray(prob.target_xyz, dtype=np.float64)
+    own = np.full(len(x), -1, dtype=np.int64)
+    m = prob.node_of_target >= 0
+    own[m] = np.searchsorted(prob.node_ptr, prob.node_of_target[m], side="right") - 1
+    rows, margin = [], np.full(len(x), np.inf)
+    for t0 in range(0, len(x), 512):
+        xs = x[t0:t0 + 512]
+        d = np.sqrt(((xs[:, None, :] - centres[None, :, :]) ** 2).sum(axis=2))
+        r = eta * radii[None, :]
+        margin[t0:t0 + 512] = (np.abs(d - r) / radii[None, :]).min(axis=1)
+        hit = d < r
+        for i in range(len(xs)):
+            js = np.nonzero(hit[i])[0]
+            rows.append(js[js != own[t0 + i]])
+    rp = np.zeros(len(x) + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    pp = np.concatenate(rows).astype(np.int32) if rows else np.zeros(0, np.int32)
+    return rp, pp, margin
 
 
 def apply(row_ptr, col, val, sigma):

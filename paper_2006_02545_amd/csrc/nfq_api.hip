@@ -11,6 +11,7 @@
 #include "nfq.h"
 #include "kernels.hpp"
 #include "near_patch.hpp"
+#include "nearlist.hpp"
 #include "adjoint.hpp"
 #include "tables.hpp"
 
@@ -137,10 +138,10 @@ void fill32(void *p, int64_t bytes, uint32_t v, hipStream_t st)
 }
 
 // Exclusive scan of a_in, b_in (length n) into a_out, b_out (length n + 1).
-nfq_status run_scan(nfq_plan *pl, int64_t n, const int64_t *a_in, const int64_t *b_in,
+nfq_status run_scan(nfq_ctx *ctx, int64_t n, const int64_t *a_in, const int64_t *b_in,
                     int64_t *a_out, int64_t *b_out, std::vector<int64_t *> &tmp)
 {
-    hipStream_t st = pl->ctx->stream;
+    hipStream_t st = ctx->stream;
     // level sizes
     std::vector<int64_t> sizes;
     int64_t m = n;
@@ -176,7 +177,7 @@ nfq_status run_scan(nfq_plan *pl, int64_t n, const int64_t *a_in, const int64_t 
     }
     hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(64), 0, st, n, a_in, b_in, a_out, b_out);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(pl->ctx, NFQ_ERR_HIP, hipGetErrorString(e));
+    if (e != hipSuccess) return fail(ctx, NFQ_ERR_HIP, hipGetErrorString(e));
     return NFQ_OK;
 }
 
@@ -218,7 +219,7 @@ nfq_status build_items(nfq_plan *pl, hipStream_t st)
         hipLaunchKernelGGL(k_patch_count, dim3(nblk(np, 256)), dim3(256), 0, st, np, pl->pair_patch,
                            pl->pair_self, pl->pcount);
     hipLaunchKernelGGL(k_patch_chunks, dim3(nblk(P, 256)), dim3(256), 0, st, P, pl->pcount, pl->nchunk);
-    nfq_status s = run_scan(pl, P, pl->pcount, pl->nchunk, pl->pptr, pl->cptr, pl->scan_tmp_p);
+    nfq_status s = run_scan(pl->ctx, P, pl->pcount, pl->nchunk, pl->pptr, pl->cptr, pl->scan_tmp_p);
     if (s != NFQ_OK) return s;
     if (np > 0)
         hipLaunchKernelGGL(k_patch_scatter, dim3(nblk(np, 256)), dim3(256), 0, st, np, pl->pair_patch,
@@ -371,7 +372,7 @@ static nfq_status prepare(nfq_plan *pl, const nfq_kernel *kern, const nfq_params
     if (NT > 0)
         hipLaunchKernelGGL(k_rowlen, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, pl->present_mask,
                            pl->rowlen, pl->npair, (unsigned long long *)nullptr, pl->flags);
-    nfq_status s = run_scan(pl, NT, pl->rowlen, pl->npair, pl->row_ptr, pl->pair_ptr, pl->scan_tmp);
+    nfq_status s = run_scan(pl->ctx, NT, pl->rowlen, pl->npair, pl->row_ptr, pl->pair_ptr, pl->scan_tmp);
     if (s != NFQ_OK) return s;
     if (NT > 0)
         hipLaunchKernelGGL(k_pairs, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, pl->row_ptr,
@@ -629,7 +630,7 @@ nfq_status nfq_plan_create(nfq_ctx *ctx, const nfq_surface *surf, const nfq_targ
     if (NT > 0)
         hipLaunchKernelGGL(k_rowlen, dim3(nblk(NT, 256)), dim3(256), 0, st, pb, pl->present_mask,
                            pl->rowlen, pl->npair, pl->counts, pl->flags);
-    nfq_status s = run_scan(pl, NT, pl->rowlen, pl->npair, row_ptr, pl->pair_ptr, pl->scan_tmp);
+    nfq_status s = run_scan(pl->ctx, NT, pl->rowlen, pl->npair, row_ptr, pl->pair_ptr, pl->scan_tmp);
     if (s != NFQ_OK) return cleanup(s);
     int hflags[kNumFlags];
     PL_TRY(hipMemcpyAsync(hflags, pl->flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
@@ -909,6 +910,149 @@ nfq_status nfq_sync(nfq_ctx *ctx)
     if (!ctx) return NFQ_ERR_INVALID_ARG;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return NFQ_OK;
+}
+
+nfq_status nfq_near_lists(nfq_ctx *ctx, const nfq_surface *surf, const nfq_targets *targets,
+                          double eta, int64_t *row_ptr, int32_t *patch, int64_t capacity,
+                          int64_t *nnz_out, double *centres, double *radii)
+{
+    if (!ctx || !surf || !targets || !row_ptr || !nnz_out)
+        return fail(ctx, NFQ_ERR_INVALID_ARG, "null argument");
+    const int64_t P = surf->P, NT = targets->NT;
+    if (P < 0 || NT < 0 || P > INT32_MAX || capacity < 0 || !(eta > 0.0) || !(eta < 1e300))
+        return fail(ctx, NFQ_ERR_INVALID_ARG, "sizes, capacity or eta out of range");
+    if ((P > 0 && (!surf->degree || !surf->node_ptr || !surf->xyz)) ||
+        (NT > 0 && (!targets->xyz || !targets->node_of_target)) || (capacity > 0 && !patch))
+        return fail(ctx, NFQ_ERR_INVALID_ARG, "null array");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    // scratch owned by this call, released on every return path
+    struct Scratch {
+        std::vector<void *> p;
+        std::vector<int64_t *> scan;
+        ~Scratch() {
+            for (void *q : p) (void)hipFree(q);
+            for (int64_t *q : scan) (void)hipFree(q);
+        }
+    } sc;
+    auto grab = [&](auto **ptr, int64_t count) -> hipError_t {
+        hipError_t e = dalloc(ptr, std::max<int64_t>(count, 1));
+        if (e == hipSuccess) sc.p.push_back((void *)*ptr);
+        return e;
+    };
+#define NL_TRY(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? NFQ_ERR_OUT_OF_MEMORY : NFQ_ERR_HIP,       \
+                        std::string(#expr " -> ") + hipGetErrorString(e_));                         \
+    } while (0)
+    Problem pb{};
+    pb.P = P;
+    pb.NT = NT;
+    pb.degree = surf->degree;
+    pb.node_ptr = surf->node_ptr;
+    pb.xyz = surf->xyz;
+    pb.txyz = targets->xyz;
+    pb.node_of_target = targets->node_of_target;
+    double *dc = centres, *dr = radii;
+    if (!dc) NL_TRY(grab(&dc, 3 * P));
+    if (!dr) NL_TRY(grab(&dr, P));
+    int *flags = nullptr;
+    NL_TRY(grab(&flags, 4));
+    fill32(flags, 4 * sizeof(int), 0u, st);
+    if (P > 0)
+        hipLaunchKernelGGL(k_balls, dim3((unsigned)std::min<int64_t>(P, 1 << 16)), dim3(64), 0, st, pb,
+                           make_tab(ctx), dc, dr, flags);
+    // extent of the targets and the largest ball
+    const int eblocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (std::max(NT, P) + 255) / 256));
+    double *part = nullptr;
+    NL_TRY(grab(&part, 7 * eblocks));
+    hipLaunchKernelGGL(k_extent, dim3(eblocks), dim3(256), 0, st, NT, pb.txyz, P, dr, part);
+    std::vector<double> hpart(7 * eblocks);
+    int hflags[4];
+    NL_TRY(hipMemcpyAsync(hpart.data(), part, hpart.size() * 8, hipMemcpyDeviceToHost, st));
+    NL_TRY(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
+    NL_TRY(hipStreamSynchronize(st));
+    if (hflags[kNearFlagUnregistered]) return fail(ctx, NFQ_ERR_NOT_REGISTERED, "patch degree not registered");
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, rmax = 0.0;
+    for (int b = 0; b < eblocks; ++b) {
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], hpart[7 * b + c]);
+            hi[c] = std::max(hi[c], hpart[7 * b + 3 + c]);
+        }
+        rmax = std::max(rmax, hpart[7 * b + 6]);
+    }
+    if (NT == 0 || P == 0) {
+        fill32(row_ptr, (NT + 1) * 8, 0u, st);
+        NL_TRY(hipStreamSynchronize(st));
+        *nnz_out = 0;
+        return NFQ_OK;
+    }
+    for (int c = 0; c < 3; ++c)
+        if (!(lo[c] <= hi[c]) || !(hi[c] - lo[c] < 1e300))
+            return fail(ctx, NFQ_ERR_INVALID_ARG, "target coordinates not finite");
+    // cells at least eta * max R wide, at most 2^24 of them
+    Grid g{};
+    double h = std::max(eta * rmax, 1e-300);
+    for (int it = 0; it < 200; ++it) {
+        int64_t tot = 1;
+        for (int c = 0; c < 3; ++c) {
+            g.n[c] = (int64_t)std::floor((hi[c] - lo[c]) / h) + 1;
+            tot = (g.n[c] > (int64_t(1) << 24)) ? (int64_t(1) << 25) : tot * g.n[c];
+            if (tot > (int64_t(1) << 24)) break;
+        }
+        if (tot <= (int64_t(1) << 24)) break;
+        h *= 1.25;
+    }
+    for (int c = 0; c < 3; ++c) g.o[c] = lo[c];
+    g.inv_h = 1.0 / h;
+    const int64_t ncell = g.n[0] * g.n[1] * g.n[2];
+    if (ncell > (int64_t(1) << 24)) return fail(ctx, NFQ_ERR_INVALID_ARG, "target extent too large for the grid");
+    // targets by cell
+    int64_t *cnt = nullptr, *cstart = nullptr, *cdummy = nullptr, *items = nullptr;
+    NL_TRY(grab(&cnt, ncell));
+    NL_TRY(grab(&cstart, ncell + 1));
+    NL_TRY(grab(&cdummy, ncell + 1));
+    NL_TRY(grab(&items, NT));
+    NL_TRY(alloc_scan_tmp(std::max(ncell, NT), sc.scan));
+    fill32(cnt, ncell * 8, 0u, st);
+    hipLaunchKernelGGL(k_cell_count, dim3(nblk(NT, 256)), dim3(256), 0, st, NT, pb.txyz, g,
+                       (unsigned long long *)cnt);
+    nfq_status s = run_scan(ctx, ncell, cnt, cnt, cstart, cdummy, sc.scan);
+    if (s != NFQ_OK) return s;
+    fill32(cnt, ncell * 8, 0u, st);
+    hipLaunchKernelGGL(k_cell_fill, dim3(nblk(NT, 256)), dim3(256), 0, st, NT, pb.txyz, g, cstart,
+                       (unsigned long long *)cnt, items);
+    // pairs per target, row pointers
+    int64_t *rowlen = nullptr, *rdummy = nullptr;
+    NL_TRY(grab(&rowlen, NT));
+    NL_TRY(grab(&rdummy, NT + 1));
+    fill32(rowlen, NT * 8, 0u, st);
+    const unsigned pblocks = (unsigned)std::min<int64_t>(P, 1 << 16);
+    hipLaunchKernelGGL(k_near_scan<false>, dim3(pblocks), dim3(64), 0, st, pb, g, eta, dc, dr, cstart,
+                       items, (unsigned long long *)rowlen, (const int64_t *)nullptr, (int32_t *)nullptr);
+    s = run_scan(ctx, NT, rowlen, rowlen, row_ptr, rdummy, sc.scan);
+    if (s != NFQ_OK) return s;
+    int64_t nnz = 0;
+    NL_TRY(hipMemcpyAsync(&nnz, row_ptr + NT, 8, hipMemcpyDeviceToHost, st));
+    NL_TRY(hipStreamSynchronize(st));
+    *nnz_out = nnz;
+    if (nnz > capacity)
+        return fail(ctx, NFQ_ERR_INVALID_ARG,
+                    "patch capacity " + std::to_string(capacity) + " < " + std::to_string(nnz) +
+                        " near pairs (row_ptr written; call again with capacity >= nnz)");
+    if (nnz > 0) {
+        fill32(rowlen, NT * 8, 0u, st);
+        hipLaunchKernelGGL(k_near_scan<true>, dim3(pblocks), dim3(64), 0, st, pb, g, eta, dc, dr,
+                           cstart, items, (unsigned long long *)rowlen, (const int64_t *)row_ptr, patch);
+        hipLaunchKernelGGL(k_row_sort, dim3(nblk(NT, 256)), dim3(256), 0, st, NT, (const int64_t *)row_ptr,
+                           patch);
+    }
+    NL_TRY(hipGetLastError());
+    NL_TRY(hipStreamSynchronize(st));
+#undef NL_TRY
     return NFQ_OK;
 }
 

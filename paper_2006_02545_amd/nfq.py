@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(HERE, "libnfq.so")
 
 NFQ_OK = 0
 NFQ_WARN_NONCONVERGED = 1
+NFQ_ERR_INVALID_ARG = -1
+NFQ_ERR_NOT_REGISTERED = -2
 STATUS = {0: "NFQ_OK", 1: "NFQ_WARN_NONCONVERGED", -1: "NFQ_ERR_INVALID_ARG",
           -2: "NFQ_ERR_NOT_REGISTERED", -3: "NFQ_ERR_DEGENERATE_PATCH",
           -4: "NFQ_ERR_SINGULAR_PAIR", -5: "NFQ_ERR_OUT_OF_MEMORY", -6: "NFQ_ERR_HIP",
@@ -23,7 +25,7 @@ STATUS = {0: "NFQ_OK", 1: "NFQ_WARN_NONCONVERGED", -1: "NFQ_ERR_INVALID_ARG",
 
 EXPORTED = ["nfq_create", "nfq_destroy", "nfq_register_degree", "nfq_plan_create",
             "nfq_generate", "nfq_apply", "nfq_adjoint", "nfq_sync", "nfq_plan_destroy",
-            "nfq_status_str", "nfq_last_error"]
+            "nfq_status_str", "nfq_last_error", "nfq_near_lists"]
 
 
 class Surface(C.Structure):
@@ -101,6 +103,9 @@ def load(path: str = LIB_PATH):
     L.nfq_apply.restype = i32
     L.nfq_sync.argtypes = [vp]
     L.nfq_sync.restype = i32
+    L.nfq_near_lists.argtypes = [vp, C.POINTER(Surface), C.POINTER(Targets), C.c_double, vp, vp,
+                                 i64, C.POINTER(i64), vp, vp]
+    L.nfq_near_lists.restype = i32
     L.nfq_plan_destroy.argtypes = [vp]
     L.nfq_plan_destroy.restype = None
     L.nfq_status_str.argtypes = [i32]
@@ -146,6 +151,38 @@ class Context:
         self._check(self.L.nfq_register_degree(self.h, int(d), uv.ctypes.data_as(C.c_void_p), wp),
                     self.h)
         self.registered[int(d)] = uv
+
+    def near_lists(self, degree, node_ptr, xyz, target_xyz, node_of_target, eta):
+        """Near lists on the device (nfq_near_lists): returns device tensors
+        (row_ptr [NT+1] int64, patch [nnz] int32, centres [P,3], radii [P])."""
+        torch = self.torch
+        dev = torch.device("cuda", self.device)
+
+        def dt(a, dtype):
+            if isinstance(a, torch.Tensor):
+                return a.to(device=dev, dtype=dtype).contiguous()
+            return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=dev)
+
+        deg, nptr, x = dt(degree, torch.int32), dt(node_ptr, torch.int64), dt(xyz, torch.float64)
+        tx, nt = dt(target_xyz, torch.float64), dt(node_of_target, torch.int64)
+        P, NT = int(deg.shape[0]), int(tx.shape[0])
+        surf = Surface(P, deg.data_ptr(), nptr.data_ptr(), x.data_ptr())
+        tg = Targets(NT, tx.data_ptr(), nt.data_ptr())
+        row_ptr = torch.empty(NT + 1, dtype=torch.int64, device=dev)
+        centres = torch.empty((P, 3), dtype=torch.float64, device=dev)
+        radii = torch.empty(P, dtype=torch.float64, device=dev)
+        nnz = C.c_int64()
+        # first call sizes the output (capacity 0), the second fills it
+        st = self.L.nfq_near_lists(self.h, C.byref(surf), C.byref(tg), float(eta), _ptr(row_ptr),
+                                   None, 0, C.byref(nnz), _ptr(centres), _ptr(radii))
+        if st < 0 and nnz.value == 0:
+            self._check(st, self.h)
+        patch = torch.empty(max(int(nnz.value), 1), dtype=torch.int32, device=dev)
+        if nnz.value > 0:
+            self._check(self.L.nfq_near_lists(self.h, C.byref(surf), C.byref(tg), float(eta),
+                                              _ptr(row_ptr), _ptr(patch), int(nnz.value),
+                                              C.byref(nnz), _ptr(centres), _ptr(radii)), self.h)
+        return row_ptr, patch[:int(nnz.value)], centres, radii
 
     def close(self):
         if getattr(self, "h", None):

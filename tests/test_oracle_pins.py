@@ -376,3 +376,37 @@ def test_method_mode_meets_error_bound():
             e = dual_norm_error(meth.pair(t, j), tru.pair(t, j), node_jacobians(meth, prob, j), w)
             worst = max(worst, e)
     assert worst <= prob.tol, worst
+
+
+def test_oracle_ball_flat_triangle():
+    """Ball of a flat patch: the parametric mean of an affine chart is the
+    vertex centroid, and the farthest lattice point is a vertex."""
+    import oracle
+    from tests.helpers import flat_patch_problem
+    verts = np.array([[0.3, -0.1, 0.2], [1.4, 0.2, -0.3], [0.1, 0.8, 0.5]])
+    for d in (1, 3, 6):
+        prob = flat_patch_problem(verts, d, None)
+        c, R = oracle.OracleRun(prob, mode=oracle.TRUTH).ball(0)
+        g = verts.mean(0)
+        assert np.abs(c - g).max() <= 1e-14
+        assert abs(R - np.linalg.norm(verts - g, axis=1).max()) <= 1e-14
+
+
+def test_oracle_near_lists_known_distances():
+    """Targets placed at known multiples of eta R from the ball centre; node
+    targets of the patch itself are never listed (own patch)."""
+    import oracle
+    from tests.helpers import flat_patch_problem
+    verts = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+    g = verts.mean(0)
+    R = np.linalg.norm(verts - g, axis=1).max()
+    eta = 1.25
+    dirn = np.array([0.3, -0.5, 0.8]) / np.linalg.norm([0.3, -0.5, 0.8])
+    scales = [0.0, 0.5, 0.999, 1.001, 2.0]
+    targets = [g + s * eta * R * dirn for s in scales]
+    prob = flat_patch_problem(verts, 3, targets, self_nodes=True)
+    rp, pp, margin = oracle.near_lists(prob, eta, g[None], np.array([R]))
+    rows = [list(pp[rp[t]:rp[t + 1]]) for t in range(prob.NT)]
+    assert rows[:5] == [[0], [0], [0], [], []]
+    assert all(r == [] for r in rows[5:])          # the patch's own nodes
+    assert margin[2] == pytest.approx(0.001 * eta, rel=1e-6)
