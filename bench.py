@@ -252,6 +252,25 @@ def main():
         torch.cuda.synchronize()
         ms_pp = (time.perf_counter() - t0) / npp * 1e3
 
+    # the GPU near-list builder on the same surface and targets (not part of
+    # the step: the generator takes the lists as input)
+    near_builder = None
+    if main_line:
+        args_nl = (prob.degree, prob.node_ptr, prob.xyz, prob.target_xyz, prob.node_of_target,
+                   prob.eta)
+        dev_args = [torch.as_tensor(a, device="cuda") if not isinstance(a, float) else a
+                    for a in args_nl]
+        ctx.near_lists(*dev_args)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            nl_rp, _, _, _ = ctx.near_lists(*dev_args)
+        torch.cuda.synchronize()
+        near_builder = {"ms": (time.perf_counter() - t0) / reps * 1e3,
+                        "pairs": int(nl_rp[-1].item()), "reps": reps,
+                        "what": "nfq_near_lists: balls, grid, count + fill + sort (two calls)"}
+
     # per-phase durations from HIP events recorded on the library's stream
     phases = {k: 0.0 for k in ("ms_builder", "ms_prep", "ms_self", "ms_near", "ms_weights")}
     st = None
@@ -300,6 +319,7 @@ def main():
             "value": prob.NT / (ms_pp * 1e-3), "unit": "target-points/s", "ms_per_step": ms_pp,
             "steps": npp},
         "graph_replay": graph,
+        "near_list_builder": near_builder,
         "phase_ms": phases,
         "gen_stats": {k: st[k] for k in ("near_pairs", "self_pairs", "visits", "checks",
                                          "nonconverged", "max_level")},
