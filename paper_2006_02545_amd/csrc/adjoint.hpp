@@ -283,7 +283,8 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_adjoint_patch(AdjArgs
                                              a.rule[3 * q + 1], a.rule[3 * q + 2] * area,
                                              s_geo + tid * GSA, tid & 15);
             }
-            __syncthreads();
+            // a single-target group reads only each thread's own node row
+            if (__builtin_popcountll(e.mask) != 1) __syncthreads();
             const double thr = tau * __builtin_ldexp(1.0, -2 * e.level);
             const int L = e.level;
             // ---- the forward's work split and test, in the same arithmetic
