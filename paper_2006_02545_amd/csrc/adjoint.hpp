@@ -180,8 +180,8 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_adjoint_patch(AdjArgs
     __shared__ double s_cm[4 * W];
     __shared__ double s_g2[4];
     __shared__ double s_nf[64];
-    __shared__ unsigned long long s_fail;
-    __shared__ int s_sp;
+    // failing-target masks of the current and the next group (alternating)
+    __shared__ unsigned long long s_fail2[2];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int grp16 = lane >> 4, l16 = lane & 15;
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_adjoint_patch(AdjArgs
             e.level = 0;
             e.child = 0;
             e.mask = count == 64 ? ~0ull : ((1ull << count) - 1ull);
-            s_sp = 1;
+            s_fail2[0] = 0ull;
         }
         __syncthreads();
         // per-wavefront moment vectors (unit l16 of each) and scalar sums
@@ -257,14 +257,14 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_adjoint_patch(AdjArgs
 #pragma unroll
         for (int v = 0; v < 9 * PL; ++v) GM[v] = 0.0;
         double SC[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // dPhi/dk, Phi_S, Phi_D
-        while (true) {
-            if (s_sp == 0) break;
-            const GroupEntry e = s_stack[s_sp - 1];
-            __syncthreads();
-            if (tid == 0) {
-                s_sp = s_sp - 1;
-                s_fail = 0ull;
-            }
+        // stack depth and failing-target words as in the forward kernel
+        int sp = 1;
+        unsigned gpar = 0;
+        while (sp > 0) {
+            const GroupEntry e = s_stack[sp - 1];
+            --sp;
+            unsigned long long *const s_fail = &s_fail2[gpar & 1];
+            if (tid == 0) s_fail2[(gpar + 1) & 1] = 0ull;
             const bool capped = ++item_groups > kGroupCap;
             const double ax = e.tri[0], ay = e.tri[1], bx = e.tri[2], by = e.tri[3];
             const double cx = e.tri[4], cy = e.tri[5];
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_adjoint_patch(AdjArgs
 #pragma unroll
                         for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = cm[i];
                     }
-                    if (tid == 0) s_fail = 1ull << s;
+                    if (tid == 0) *s_fail = 1ull << s;
                 }
             } else {
                 unsigned long long mk = e.mask;
@@ -383,13 +383,13 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_adjoint_patch(AdjArgs
                         double *dst = mptr(L + 1, grp16, s);
 #pragma unroll
                         for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = acc[i];
-                        if (lane == 0) atomicOr(&s_fail, 1ull << s);
+                        if (lane == 0) atomicOr(s_fail, 1ull << s);
                     }
                 }
             }
             __syncthreads();
             // ---- gradient over the children nodes for the accepting targets
-            const unsigned long long accm = e.mask & ~s_fail;
+            const unsigned long long accm = e.mask & ~*s_fail;
             if (accm != 0ull) {
                 const double *g = s_geo + tid * GSA;
                 const double X[3] = {g[G0], g[G0 + 1], g[G0 + 2]};
@@ -472,9 +472,10 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_adjoint_patch(AdjArgs
                 }
             }
             __syncthreads();
-            if (tid == 0 && s_fail != 0ull) {
+            const unsigned long long fail = *s_fail;
+            if (tid == 0 && fail != 0ull) {
                 for (int c = 3; c >= 0; --c) {
-                    GroupEntry &ne = s_stack[s_sp];
+                    GroupEntry &ne = s_stack[sp + 3 - c];
                     double t0x, t0y, t1x, t1y, t2x, t2y;
                     if (c == 0) { t0x = ax; t0y = ay; t1x = abx; t1y = aby; t2x = cax; t2y = cay; }
                     else if (c == 1) { t0x = abx; t0y = aby; t1x = bx; t1y = by; t2x = bcx; t2y = bcy; }
@@ -484,10 +485,11 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_adjoint_patch(AdjArgs
                     ne.tri[4] = t2x; ne.tri[5] = t2y;
                     ne.level = L + 1;
                     ne.child = c;
-                    ne.mask = s_fail;
-                    s_sp = s_sp + 1;
+                    ne.mask = fail;
                 }
             }
+            if (fail != 0ull) sp += 4;
+            ++gpar;
             __syncthreads();
         }
         // per-wavefront parts to LDS (over the geometry rows, free here), then

@@ -264,8 +264,8 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
     __shared__ double s_cm[4 * W];
     __shared__ double s_g2[4];
     __shared__ double s_nf[64];
-    __shared__ unsigned long long s_fail;
-    __shared__ int s_sp;
+    // failing-target masks of the current and the next group (alternating)
+    __shared__ unsigned long long s_fail2[2];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int grp16 = lane >> 4, l16 = lane & 15;
@@ -341,17 +341,20 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
             e.level = 0;
             e.child = 0;
             e.mask = count == 64 ? ~0ull : ((1ull << count) - 1ull);
-            s_sp = 1;
+            s_fail2[0] = 0ull;
         }
         __syncthreads();
-        while (true) {
-            if (s_sp == 0) break;
-            const GroupEntry e = s_stack[s_sp - 1];
-            __syncthreads();
-            if (tid == 0) {
-                s_sp = s_sp - 1;
-                s_fail = 0ull;
-            }
+        // The stack depth is uniform and kept by every thread; tid 0 writes
+        // the pushed entries.  Group g collects its failing targets in
+        // s_fail2[g & 1] and clears the other word for group g + 1 (whose
+        // last readers finished before the previous group's final barrier).
+        int sp = 1;
+        unsigned gpar = 0;
+        while (sp > 0) {
+            const GroupEntry e = s_stack[sp - 1];
+            --sp;
+            unsigned long long *const s_fail = &s_fail2[gpar & 1];
+            if (tid == 0) s_fail2[(gpar + 1) & 1] = 0ull;
             const bool capped = ++item_groups > kGroupCap;
             // children geometry: thread tid -> child tid / 64, node tid % 64,
             // read by row lane tid % 16
@@ -451,7 +454,7 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
 #pragma unroll
                             for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = cm[i];
                         }
-                        if (tid == 0) s_fail = 1ull << s;
+                        if (tid == 0) *s_fail = 1ull << s;
                     }
                 } else {
                 // targets of the mask, the k-th set bit to wavefront (k + kofs) % 4
@@ -519,15 +522,16 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                         double *dst = mptr(L + 1, grp16, s);
 #pragma unroll
                         for (int i = 0; i < PL; ++i) dst[PL * l16 + i] = acc[i];
-                        if (lane == 0) atomicOr(&s_fail, 1ull << s);
+                        if (lane == 0) atomicOr(s_fail, 1ull << s);
                     }
                 }
             }
             __syncthreads();
-            if (tid == 0 && s_fail != 0ull) {
+            const unsigned long long fail = *s_fail;
+            if (tid == 0 && fail != 0ull) {
                 // push children 3..0 so that child 0 is processed next
                 for (int c = 3; c >= 0; --c) {
-                    GroupEntry &ne = s_stack[s_sp];
+                    GroupEntry &ne = s_stack[sp + 3 - c];
                     double t0x, t0y, t1x, t1y, t2x, t2y;
                     if (c == 0) { t0x = ax; t0y = ay; t1x = abx; t1y = aby; t2x = cax; t2y = cay; }
                     else if (c == 1) { t0x = abx; t0y = aby; t1x = bx; t1y = by; t2x = bcx; t2y = bcy; }
@@ -537,10 +541,11 @@ __global__ __launch_bounds__(256, (D <= 4 ? 2 : 1)) void k_near_patch(PatchArgs 
                     ne.tri[4] = t2x; ne.tri[5] = t2y;
                     ne.level = L + 1;
                     ne.child = c;
-                    ne.mask = s_fail;
-                    s_sp = s_sp + 1;
+                    ne.mask = fail;
                 }
             }
+            if (fail != 0ull) sp += 4;
+            ++gpar;
             __syncthreads();
         }
         if (S::TOT_LDS)
