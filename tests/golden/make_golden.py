@@ -38,6 +38,11 @@ WORKLOADS = {
     "cfie_sphere1280_d4": (lambda: S.config(1), 160),
     "cfie_sphere320_d4_k5": (lambda: S.config(3), 120),
     "mixed_small_d1to8": (small_mixed, 160),
+    # smallest degrees, real double layer and a tighter tolerance
+    "laplace_d_sphere80_d1": (lambda: S.sphere_problem(1, 1, 0.0, 1.0, 0.0, 1e-6, seed=8,
+                                                       density="uniform"), None),
+    "cfie_sphere80_d2_k3": (lambda: S.sphere_problem(1, 2, -3j, 1.0, 3.0, 1e-9, seed=9,
+                                                     density="gauss"), 160),
     # full-size workloads, sampled rows
     "mixed_ellipsoid_torus": (lambda: S.config(2), 48),
     "star200k_d6": (lambda: S.config(4), 24),
