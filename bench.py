@@ -91,9 +91,13 @@ def cpu_baseline(seconds, workers, cfg=1):
 # --copy-calibration 1024: FETCH_SIZE reads 0.5 GiB, WRITE_SIZE 1 GiB), valid
 # for the kernel sources with this digest.
 TRAFFIC_RECORD = {
-    "sources_sha256": "cfbfe41a871622c4ffcace426572b48f7d35a2370a2c3e9f3c9d8b7d77460d01",
-    "fetch_kib": 178853.3, "write_kib": 374629.3,
+    "sources_sha256": "356cb9f19fe2f81c71736779fd27243997c37c3faefc319be5c16b44d664021e",
+    "fetch_kib": 173119.0, "write_kib": 371788.6,
     "fetch_scale": 2.0, "write_scale": 1.0,
+    # FP64 VALU wave instructions per launch (SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64),
+    # one rocprofv3 --pmc pass: hardware-counted flops = 64 lanes x (2 FMA + MUL
+    # + ADD + TRANS)
+    "fma_f64": 724992720, "mul_f64": 315824200, "add_f64": 142378440, "trans_f64": 6997280, "valu": 2007371962,
 }
 NEAR_SOURCES = ["near_patch.hpp", "kernels.hpp", "device.hpp", "fastmath.hpp", "koorn.hpp"]
 
@@ -105,6 +109,15 @@ def near_sources_digest():
         with open(os.path.join(ROOT, "paper_2006_02545_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def near_hw_flops():
+    """Hardware-counted FP64 flops of one near-kernel launch, or None when the
+    counters were taken on other kernel sources."""
+    r = TRAFFIC_RECORD
+    if r["sources_sha256"] != near_sources_digest():
+        return None
+    return 64.0 * (2.0 * r["fma_f64"] + r["mul_f64"] + r["add_f64"] + r["trans_f64"])
 
 
 def near_traffic():
@@ -294,6 +307,11 @@ def main():
                     "frac": achieved / PEAK_FP64_TFLOPS,
                     "traffic": near_traffic() if main_line else None,
                     "flops_per_launch": flops_near, "ms_per_launch": phases["ms_near"]}
+        hw = near_hw_flops() if main_line else None
+        if hw is not None:
+            roofline["hw_counted"] = {"flops_per_launch": hw,
+                                      "tflops": hw / (phases["ms_near"] * 1e-3) / 1e12,
+                                      "frac": hw / (phases["ms_near"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
     out = {
         "metric": METRIC,
         "value": value,

@@ -70,6 +70,31 @@ def test_near_lists_match_oracle(ctx, name):
     print("%d targets, %d pairs, %d near-tie rows skipped" % (prob.NT, rp[-1], ties), flush=True)
 
 
+def test_near_lists_off_surface_targets(ctx):
+    """Off-surface targets (node_of_target = -1) 2 % outside and 3 % inside
+    the 320-patch sphere: no own patch is excluded."""
+    import oracle
+    from dataclasses import replace
+    print("near-list case off-surface targets, sphere320", flush=True)
+    base = _problem("cfie_sphere320_d4_k5")
+    rng = np.random.default_rng(5)
+    pick = rng.choice(base.NT, 600, replace=False)
+    x = base.target_xyz[pick] * np.where(np.arange(600) % 2 == 0, 1.02, 0.97)[:, None]
+    prob = replace(base, target_xyz=x, node_of_target=np.full(600, -1, np.int64))
+    rp, pp, c, r = _gpu_lists(ctx, prob)
+    run = oracle.OracleRun(base, mode=oracle.TRUTH)
+    oc = np.zeros((prob.P, 3))
+    orad = np.zeros(prob.P)
+    for j in range(prob.P):
+        oc[j], orad[j] = run.ball(j)
+    orp, opp, margin = oracle.near_lists(prob, prob.eta, oc, orad)
+    for t in range(prob.NT):
+        if margin[t] < TIE:
+            continue
+        assert np.array_equal(pp[rp[t]:rp[t + 1]], opp[orp[t]:orp[t + 1]]), t
+    assert rp[-1] > 0
+
+
 def test_near_lists_edge_cases(ctx):
     """No targets; no patches near any target; capacity too small."""
     import torch
