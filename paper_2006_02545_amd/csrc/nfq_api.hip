@@ -995,7 +995,8 @@ nfq_status nfq_near_lists(nfq_ctx *ctx, const nfq_surface *surf, const nfq_targe
             return fail(ctx, NFQ_ERR_INVALID_ARG, "target coordinates not finite");
     // cells at least eta * max R wide, at most 2^24 of them
     Grid g{};
-    double h = std::max(eta * rmax, 1e-300);
+    const double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+    double h = std::max(std::max(eta * rmax, ext / 256.0), 1e-300);
     for (int it = 0; it < 200; ++it) {
         int64_t tot = 1;
         for (int c = 0; c < 3; ++c) {
