@@ -307,6 +307,9 @@ def main():
                     "frac": achieved / PEAK_FP64_TFLOPS,
                     "traffic": near_traffic() if main_line else None,
                     "flops_per_launch": flops_near, "ms_per_launch": phases["ms_near"]}
+        if roofline["traffic"] is not None:
+            roofline["hbm_gbps"] = roofline["traffic"] / (phases["ms_near"] * 1e-3) / 1e9
+            roofline["hbm_frac"] = roofline["hbm_gbps"] / 8000.0
         hw = near_hw_flops() if main_line else None
         if hw is not None:
             roofline["hw_counted"] = {"flops_per_launch": hw,
