@@ -192,7 +192,9 @@ nfq_status nfq_apply(nfq_plan *plan, const int32_t *col, const void *val, const 
  * the target position for node targets; each node may be the target of at
  * most one target), grad_k [1] = dPhi/dk at fixed alpha, beta, and dphi_dab
  * [2] = (dPhi/dalpha, dPhi/dbeta) or NULL.  Deterministic.  Not part of the
- * paper (a companion for shape optimisation and inverse problems). */
+ * paper (a companion for shape optimisation and inverse problems).
+ * Errors: as nfq_generate; UNSUPPORTED when near pairs on degree-7 patches are
+ * present (that kernel instance is disabled: it returned non-finite values). */
 nfq_status nfq_adjoint(nfq_plan *plan, const nfq_kernel *kern, const nfq_params *params,
                        const void *sigma, const void *lambda, void *grad_xyz, void *grad_k,
                        void *dphi_dab);

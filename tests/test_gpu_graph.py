@@ -6,11 +6,13 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 
-def test_generate_graph_replay():
+@pytest.mark.parametrize("name", ["cfie_sphere320_d4_k5", "mixed_small_d1to8"])
+def test_generate_graph_replay(name):
     import torch
-    from paper_2006_02545_amd import nfq, surfaces
-    print("graph replay case cfie_sphere320_d4_k5", flush=True)
-    prob = surfaces.config(3)
+    from paper_2006_02545_amd import nfq
+    from tests.golden.make_golden import WORKLOADS
+    print("graph replay case", name, flush=True)
+    prob = WORKLOADS[name][0]()
     s = torch.cuda.Stream()
     ctx = nfq.Context(0, stream=s)
     plan = nfq.plan_for(ctx, prob)

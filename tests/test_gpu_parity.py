@@ -91,6 +91,34 @@ def test_parity_against_oracle(ctx, name):
     print("worst dual-norm error / eps = %.3g over %d blocks; stats %s" % (worst, n, st))
 
 
+@pytest.mark.parametrize("name", ["laplace_s_sphere80_d3", "cfie_sphere320_d4_k5",
+                                  "mixed_small_d1to8"])
+def test_per_pair_path_parity(ctx, name):
+    """The per-pair comparator kernel (one wavefront per pair, no geometry
+    reuse) against the same truth rows."""
+    from paper_2006_02545_amd import nfq
+    print("per-pair parity case", name, flush=True)
+    prob = _problem(name)
+    plan = nfq.plan_for(ctx, prob)
+    col, val, st = plan.generate(prob.alpha, prob.beta, prob.k, prob.tol, per_pair=True)
+    assert st["nonconverged"] == 0
+    rp = plan.row_ptr.cpu().numpy()
+    worst, n = _check_against_golden(name, prob, rp, val.cpu().numpy())
+    print("per-pair path: worst dual-norm error / eps = %.3g over %d blocks" % (worst, n))
+
+
+def test_apply_complex_matches_oracle_apply(ctx):
+    import oracle
+    import torch
+    from paper_2006_02545_amd import nfq
+    prob = _problem("cfie_sphere320_d4_k5")
+    plan = nfq.plan_for(ctx, prob)
+    col, val, _ = plan.generate(prob.alpha, prob.beta, prob.k, prob.tol)
+    y = plan.apply(col, val, torch.as_tensor(prob.sigma)).cpu().numpy()
+    ref = oracle.apply(plan.row_ptr.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy(), prob.sigma)
+    assert np.allclose(y, ref, rtol=1e-13, atol=1e-15 * np.abs(ref).max())
+
+
 def test_structure_and_determinism(ctx):
     """Row pointers and columns bit-exact; two runs bitwise identical."""
     from paper_2006_02545_amd import nfq
