@@ -29,6 +29,7 @@ struct nfq_ctx {
 
 struct nfq_plan {
     nfq_ctx *ctx = nullptr;
+    int device = 0;   // kept here so that destroying a plan never reads its context
     Problem pb{};
     int64_t nnz = 0, npairs = 0;
     int64_t *row_ptr = nullptr;      // caller's
@@ -537,7 +538,7 @@ nfq_status nfq_register_degree(nfq_ctx *ctx, int d, const double *ref_uv, const 
 void nfq_plan_destroy(nfq_plan *pl)
 {
     if (!pl) return;
-    (void)hipSetDevice(pl->ctx->device);
+    (void)hipSetDevice(pl->device);
     void *ptrs[] = {pl->rowlen, pl->npair, pl->pair_ptr, pl->pair_tgt, pl->pair_patch, pl->pair_self,
                     pl->pair_off, pl->grp, pl->seg_start, pl->cursor, pl->coef, pl->coef_rel, pl->tau, pl->rho, pl->stack,
                     pl->flags, pl->stats, pl->counts};
@@ -573,6 +574,7 @@ nfq_status nfq_plan_create(nfq_ctx *ctx, const nfq_surface *surf, const nfq_targ
     nfq_plan *pl = new (std::nothrow) nfq_plan;
     if (!pl) return fail(ctx, NFQ_ERR_OUT_OF_MEMORY, "plan");
     pl->ctx = ctx;
+    pl->device = ctx->device;
     hipStream_t st = ctx->stream;
     Problem &pb = pl->pb;
     pb.P = surf->P;

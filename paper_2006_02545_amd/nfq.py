@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -136,6 +137,9 @@ class Context:
                                       C.byref(h)), None)
         self.h = h
         self.registered = {}
+        # plans of this context, closed before it (whatever order the
+        # garbage collector finalises them in)
+        self._plans = weakref.WeakSet()
 
     def _check(self, st, h=None):
         if st < 0:
@@ -186,6 +190,8 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            for p in list(getattr(self, "_plans", ())):
+                p.close()
             self.L.nfq_destroy(self.h)
             self.h = None
 
@@ -233,6 +239,7 @@ class Plan:
                                          _ptr(self.row_ptr)), ctx.h)
         self.h = h
         self.nnz = int(nnz.value)
+        ctx._plans.add(self)
 
     def generate(self, alpha, beta, k, tol, loosen=1.0, max_depth=16, self_nr=0, self_na=0,
                  col=None, val=None, stats=True, timing=False, per_pair=False, min_depth=0):
