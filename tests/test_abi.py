@@ -64,3 +64,13 @@ def test_near_lists_well_formed(cfg):
         assert own[t] not in row
         for j in row:
             assert np.linalg.norm(p.target_xyz[t] - p.centers[j]) < p.eta * p.radii[j]
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; --gpus above 1 exits with a message."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
