@@ -43,6 +43,10 @@ WORKLOADS = {
                                                        density="uniform"), None),
     "cfie_sphere80_d2_k3": (lambda: S.sphere_problem(1, 2, -3j, 1.0, 3.0, 1e-9, seed=9,
                                                      density="gauss"), 160),
+    # real Laplace double layer on the small mixed-degree fixture (real-kernel
+    # instances of every degree)
+    "laplace_d_mixed_small": (lambda: S.mixed_problem(seed=11, tol=1e-8, k=0.0, ell_freq=3,
+                                                      tor_grid=(16, 6), dmin=2, dmax=8), 160),
     # full-size workloads, sampled rows
     "mixed_ellipsoid_torus": (lambda: S.config(2), 48),
     "star200k_d6": (lambda: S.config(4), 24),

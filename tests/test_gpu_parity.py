@@ -78,7 +78,8 @@ def _check_against_golden(name, prob, rp, val, factor=10.0):
 
 @pytest.mark.parametrize("name", ["laplace_s_sphere80_d3", "cfie_sphere1280_d4",
                                   "cfie_sphere320_d4_k5", "mixed_small_d1to8",
-                                  "laplace_d_sphere80_d1", "cfie_sphere80_d2_k3"])
+                                  "laplace_d_sphere80_d1", "cfie_sphere80_d2_k3",
+                                  "laplace_d_mixed_small"])
 def test_parity_against_oracle(ctx, name):
     from paper_2006_02545_amd import nfq
     print("parity case", name, flush=True)
