@@ -80,9 +80,19 @@ def cpu_baseline(seconds, workers, cfg=1):
         done = sum(r[0] for r in res)
         rate = sum(r[0] / r[1] for r in res)
         el = max(r[1] for r in res)
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": rate, "unit": "target-points/s", "cores": workers, "kind": "oracle",
             "sample": "%d random target rows of the same workload (near + self blocks), oracle "
-                      "method mode, %d process(es) x 1 thread, %.1f s each" % (done, workers, el)}
+                      "method mode, %d process(es) x 1 thread, %.1f s each, %s"
+                      % (done, workers, el, cpu)}
 
 
 # HBM traffic of the near kernel per launch on this workload, from two
